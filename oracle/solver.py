@@ -1,0 +1,171 @@
+"""The coupled time step and the nondimensional output fields.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+State after n steps: the pre-collision populations f^n and g^n, stored as
+deviations from hydrostatic reference rows (see lbm.py).  One step
+n -> n+1, in the order the paper's equations give it:
+  1. rho_c^n = sum_i g_i^n                                 (Eq. 6)
+  2. phi^n from the Poisson problem with s = -rho_c^n/eps (Eq. 4, 18-25)
+  3. E^n = -grad phi^n (central differences)
+  4. rho = sum f_i, F = rho_c E (+ test body force), u from Eq. 7,
+     charge transport velocity v = u - mu_b grad(phi) = u + K E (Eq. 11)
+  5. TRT collision of f with the source of Eq. 12 (Eq. 8, 13, 15) and of g
+     (Eq. 9, 14), with the same-time-level phi^n
+  6. streaming with the electrode conditions of Table I.
+"""
+
+import numpy as np
+
+from . import hydrostatic, lbm, poisson, splitmix
+from .lattice import WI, Params, lattice_constants
+
+
+def round_bits(v, bits=40):
+    """v rounded to `bits` significant bits (elementwise)."""
+    v = np.asarray(v, dtype=np.float64)
+    m, e = np.frexp(v)
+    return np.ldexp(np.round(m * 2.0**bits), e - bits)
+
+
+def hydrostatic_rows(p: Params, lc):
+    """Lattice-unit reference rows of the closed-form state at y = j + 1/2.
+
+    Returns (rho_c_ref, s_ref):
+      rho_c_ref -- the closed-form charge profile (Eq. 27)
+      s_ref     -- slope of the reference density rho_ref(y) = 1 + s_ref
+                   (y - H/2), which balances the uniform closed-form force
+                   density F0 = rho_c E = eps C E0 / H^3 with the lattice
+                   pressure gradient: cs2 d(rho)/dy = F0, so s_ref = 3 F0.
+    """
+    ny = p.ny
+    H = lc.H
+    yj = (np.arange(ny) + 0.5) / ny
+    e0 = hydrostatic.field_at_injector(p.C)
+    _, rc_nd, _ = hydrostatic.profiles(p.C, yj)
+    rho_c_ref = lc.eps / H**2 * rc_nd
+    F0 = lc.eps * p.C * e0 / H**3
+    return rho_c_ref, 3.0 * F0
+
+
+def charge_noise(p: Params) -> np.ndarray:
+    """xi(x, j) in [-1, 1): k-th SplitMix64 output, k = j*nx + x, seed + instance."""
+    xi = splitmix.uniform_pm1(p.seed + p.instance_id, p.nx * p.ny)
+    return xi.reshape(p.ny, p.nx)
+
+
+def eq29_velocity(p: Params, lc):
+    """Divergence-free, no-slip perturbation of Eq. 29, in lattice velocity.
+
+    x and y in units of the gap H (x = x_node / H, y = (j + 1/2) / H), Lx =
+    nx / ny, Ly = 1, amplitude 1e-3 in units of u0 = K / H.
+    """
+    nx, ny = p.nx, p.ny
+    x = (np.arange(nx) / ny)[None, :]
+    y = ((np.arange(ny) + 0.5) / ny)[:, None]
+    Lx, Ly = nx / ny, 1.0
+    ux = 1e-3 * lc.u0 * Lx * np.sin(2 * np.pi * y / Ly) * np.sin(2 * np.pi * x / Lx)
+    uy = 1e-3 * lc.u0 * Ly * (np.cos(2 * np.pi * y / Ly) - 1.0) * np.cos(2 * np.pi * x / Lx)
+    return ux, uy
+
+
+class Oracle:
+    def __init__(self, p: Params):
+        self.p = p
+        self.lc = lc = lattice_constants(p)
+        nx, ny = p.nx, p.ny
+        self.n = 0
+        self.bx = float(p.body_force_x)
+        if p.init_mode == "rest":
+            rho_c_ref, s_ref = np.zeros(ny), 0.0
+        else:
+            rho_c_ref, s_ref = hydrostatic_rows(p, lc)
+        # reference rows, rounded so that w_i times them is exact (see lbm.py)
+        self.s_ref = 36.0 * float(round_bits(s_ref / 36.0))
+        self.rho_ref = 1.0 + self.s_ref * ((np.arange(ny) + 0.5) - 0.5 * lc.H)
+        q = round_bits(rho_c_ref / 36.0)
+        self.r = 36.0 * q  # reference charge row
+        self.R = (36.0 * WI)[:, None] * q[None, :]  # R_i(y) = w_i r(y), exact
+        if p.init_mode == "rest":
+            self.ft = np.zeros((9, ny, nx))
+            self.gt = np.zeros((9, ny, nx))
+            return
+        rho_c0 = np.broadcast_to(rho_c_ref[:, None], (ny, nx)).copy()
+        ux0 = np.zeros((ny, nx))
+        uy0 = np.zeros((ny, nx))
+        if p.init_mode == "noise":
+            rho_c0 = rho_c0 * (1.0 + p.noise_amp * charge_noise(p))
+        elif p.init_mode == "eq29":
+            ux0, uy0 = eq29_velocity(p, lc)
+        else:
+            raise ValueError(f"unknown init_mode {p.init_mode!r}")
+        ex0, ey0 = poisson.electric_field(*poisson.solve_split(rho_c0, lc.eps))
+        rho = np.broadcast_to(self.rho_ref[:, None], (ny, nx))
+        # f^0 = f^eq(rho_ref, u0), g^0 = g^eq(rho_c^0, u0 + K E^0)
+        self.ft = lbm.equilibrium_deviation(np.zeros((ny, nx)), rho, ux0, uy0)
+        drc0 = rho_c0 - self.r[:, None]
+        self.gt = lbm.charge_equilibrium_deviation(drc0, rho_c0, ux0 + lc.K * ex0, uy0 + lc.K * ey0)
+
+    # ---- pieces of one step -------------------------------------------------
+    def macroscopic(self):
+        """Steps 1-4 on the current pre-collision state."""
+        lc = self.lc
+        drc = lbm.charge_deviation(self.gt)
+        rho_c = self.r[:, None] + drc
+        phi_mean, phi_fluct = poisson.solve_split(rho_c, lc.eps)
+        ex, ey = poisson.electric_field(phi_mean, phi_fluct)
+        phi = phi_mean[:, None] + phi_fluct
+        drho = lbm.density_deviation(self.ft)
+        rho = self.rho_ref[:, None] + drho
+        fx = rho_c * ex + self.bx
+        fy = rho_c * ey
+        ux, uy = lbm.velocity(self.ft, rho, fx, fy)
+        return dict(rho_c=rho_c, drc=drc, phi=phi, phi_mean=phi_mean, ex=ex, ey=ey,
+                    drho=drho, rho=rho, fx=fx, fy=fy, ux=ux, uy=uy)
+
+    def collide(self, m):
+        lc = self.lc
+        om = lc.omega
+        feq = lbm.equilibrium_deviation(m["drho"], m["rho"], m["ux"], m["uy"])
+        src = lbm.forcing(m["ux"], m["uy"], m["fx"], m["fy"])
+        ft_post = lbm.trt_collide(self.ft, feq, om["wp"], om["wm"], src)
+        vx = m["ux"] + lc.K * m["ex"]
+        vy = m["uy"] + lc.K * m["ey"]
+        geq = lbm.charge_equilibrium_deviation(m["drc"], m["rho_c"], vx, vy)
+        gt_post = lbm.trt_collide(self.gt, geq, om["wgp"], om["wgm"])
+        return ft_post, gt_post
+
+    def step(self, n: int = 1):
+        for _ in range(n):
+            m = self.macroscopic()
+            ft_post, gt_post = self.collide(m)
+            self.ft = lbm.stream_fluid(ft_post, self.s_ref)
+            self.gt = lbm.stream_charge(gt_post, self.R, self.lc.rho0)
+            self.n += 1
+        return self
+
+    # ---- full populations (diagnostics and tests) --------------------------
+    def full(self, ft, gt):
+        """Full populations f, g from deviations of shape (9, ny, nx)."""
+        f = ft + WI[:, None, None] * self.rho_ref[None, :, None]
+        g = gt + self.R[:, :, None]
+        return f, g
+
+    # ---- outputs ----------------------------------------------------------
+    def fields(self):
+        """Nondimensional fields of the current state.
+
+        rho: lattice density (drho = rho - rho_ref, the departure from the
+        hydrostatic reference row); u in u0 = K/H; rho_c in eps/H^2 (so
+        rho_c = C at the injector); phi in the applied potential difference.
+        """
+        m = self.macroscopic()
+        lc = self.lc
+        return dict(
+            rho=m["rho"],
+            drho=m["drho"],
+            ux=m["ux"] / lc.u0,
+            uy=m["uy"] / lc.u0,
+            rho_c=m["rho_c"] * lc.H**2 / lc.eps,
+            phi=m["phi"],
+        )
