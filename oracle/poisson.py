@@ -79,51 +79,79 @@ def solve_spectral_rhs(s_hat: np.ndarray, nx: int, phi_lower: float = 1.0, phi_u
     return thomas(ones, diag, ones, rhs)
 
 
+def mean_mode(sbar: np.ndarray, phi_lower: float = 1.0, phi_upper: float = 0.0):
+    """The x-mean (m = 0) part of the Poisson problem, by integrating Gauss's
+    law twice.
+
+    With D(j) = phi(j+1) - phi(j) for j = -1 .. ny-1 (the ghost rows
+    included), the 3-point equation of row j reads D(j) - D(j-1) = sbar(j),
+    so D(j) = D(-1) + S(j) with S the running sum of sbar.  The ghost rules
+    give D(-1) = 2 (phi(0) - phi_lower) and D(ny-1) = 2 (phi_upper -
+    phi(ny-1)); eliminating phi(0) yields
+        D(-1) = (phi_upper - phi_lower) / ny - (S(ny-1) + 2 sum_{k<ny-1} S(k)) / (2 ny)
+    with no cancellation.  This is the same tridiagonal system the other
+    modes solve; the flux form keeps the round-off of the mean field at the
+    level of the sums instead of the O(1) potential.
+
+    Returns (phi_mean of length ny, D of length ny + 1 holding D(-1) .. D(ny-1)).
+    """
+    ny = sbar.size
+    S = np.cumsum(sbar)
+    T = S[: ny - 1].sum()
+    d_lower = (phi_upper - phi_lower) / ny - (S[ny - 1] + 2.0 * T) / (2.0 * ny)
+    D = np.concatenate([[d_lower], d_lower + S])
+    phi0 = phi_lower + 0.5 * d_lower
+    phi_mean = phi0 + np.concatenate([[0.0], np.cumsum(D[1:ny])])
+    return phi_mean, D
+
+
 def solve_split(rho_c: np.ndarray, eps: float, phi_lower: float = 1.0, phi_upper: float = 0.0):
-    """The potential as (x-mean row, fluctuation) from the charge density.
+    """The potential as x-mean row and fluctuation from the charge density.
 
     phi(x, y) = phi_mean(y) + phi_fluct(x, y), where phi_mean comes from the
-    m = 0 mode alone and phi_fluct from the m >= 1 modes.  Keeping the two
-    apart is an exact identity; it stops the O(1) rounding of phi from
-    swamping the small transverse field that the fluctuation carries.
+    m = 0 mode (solved in flux form by mean_mode) and phi_fluct from the
+    m >= 1 modes (tridiagonal per mode).  Keeping the two apart is an exact
+    identity; it stops the O(1) rounding of phi from swamping the small
+    fields that the transverse modes and the mean flux carry.
+
+    Returns (phi_mean, D, phi_fluct); D are the mean-row differences of
+    mean_mode.
     """
     ny, nx = rho_c.shape
     s = -rho_c / eps  # Eq. 4
     s_hat = dft_x(s)  # Eq. 19
-    phi_hat = solve_spectral_rhs(s_hat, nx, phi_lower, phi_upper)  # Eq. 20, 24-25
-    phi_mean = phi_hat[:, 0].real / nx
-    fl = phi_hat.copy()
-    fl[:, 0] = 0.0
-    phi_fluct = idft_x(fl).real
-    return phi_mean, phi_fluct
+    phi_mean, D = mean_mode(s_hat[:, 0].real / nx, phi_lower, phi_upper)
+    fl_hat = s_hat.copy()
+    fl_hat[:, 0] = 0.0
+    # m >= 1: homogeneous Dirichlet ghosts (the boundary values live in m = 0)
+    phi_hat = solve_spectral_rhs(fl_hat, nx, 0.0, 0.0)  # Eq. 20, 24-25
+    phi_hat[:, 0] = 0.0
+    phi_fluct = idft_x(phi_hat).real
+    return phi_mean, D, phi_fluct
 
 
 def solve(rho_c: np.ndarray, eps: float, phi_lower: float = 1.0, phi_upper: float = 0.0):
     """phi on the (ny, nx) node grid from the charge density (Eq. 4, 18-25)."""
-    phi_mean, phi_fluct = solve_split(rho_c, eps, phi_lower, phi_upper)
+    phi_mean, _, phi_fluct = solve_split(rho_c, eps, phi_lower, phi_upper)
     return phi_mean[:, None] + phi_fluct
 
 
-def electric_field(phi_mean: np.ndarray, phi_fluct: np.ndarray,
-                   phi_lower: float = 1.0, phi_upper: float = 0.0):
+def electric_field(D: np.ndarray, phi_fluct: np.ndarray):
     """E = -grad(phi) by second-order central differences.
 
     The paper does not state how the gradient for the force (Eq. 7, 12) and
     the drift (Eq. 11) is formed; this uses central differences, periodic in
     x, with the same ghost values at the electrodes as the Poisson solve.
-    The mean row and the fluctuation are differenced separately (the ghost
-    rule is linear, so the mean row takes the Dirichlet values and the
-    fluctuation takes zero).
+    The mean row enters through its differences D (mean_mode):
+    -(phi(j+1) - phi(j-1)) / 2 = -(D(j) + D(j-1)) / 2; the fluctuation has
+    zero ghost values (phi_fluct(-1) = -phi_fluct(0), likewise at the top).
     """
     ny, nx = phi_fluct.shape
-    mean_ext = np.empty(ny + 2)
-    mean_ext[1:-1] = phi_mean
-    mean_ext[0] = 2.0 * phi_lower - phi_mean[0]
-    mean_ext[-1] = 2.0 * phi_upper - phi_mean[-1]
     fl_ext = np.empty((ny + 2, nx))
     fl_ext[1:-1] = phi_fluct
     fl_ext[0] = -phi_fluct[0]
     fl_ext[-1] = -phi_fluct[-1]
-    ey = -(mean_ext[2:] - mean_ext[:-2])[:, None] / 2.0 - (fl_ext[2:] - fl_ext[:-2]) / 2.0
+    ey_mean = -(D[1:] + D[:-1]) / 2.0
+    ey = ey_mean[:, None] - (fl_ext[2:] - fl_ext[:-2]) / 2.0
     ex = -(np.roll(phi_fluct, -1, axis=1) - np.roll(phi_fluct, 1, axis=1)) / 2.0
     return ex, ey

@@ -99,7 +99,8 @@ class Oracle:
             ux0, uy0 = eq29_velocity(p, lc)
         else:
             raise ValueError(f"unknown init_mode {p.init_mode!r}")
-        ex0, ey0 = poisson.electric_field(*poisson.solve_split(rho_c0, lc.eps))
+        _, D0, fl0 = poisson.solve_split(rho_c0, lc.eps)
+        ex0, ey0 = poisson.electric_field(D0, fl0)
         rho = np.broadcast_to(self.rho_ref[:, None], (ny, nx))
         # f^0 = f^eq(rho_ref, u0), g^0 = g^eq(rho_c^0, u0 + K E^0)
         self.ft = lbm.equilibrium_deviation(np.zeros((ny, nx)), rho, ux0, uy0)
@@ -112,8 +113,8 @@ class Oracle:
         lc = self.lc
         drc = lbm.charge_deviation(self.gt)
         rho_c = self.r[:, None] + drc
-        phi_mean, phi_fluct = poisson.solve_split(rho_c, lc.eps)
-        ex, ey = poisson.electric_field(phi_mean, phi_fluct)
+        phi_mean, D, phi_fluct = poisson.solve_split(rho_c, lc.eps)
+        ex, ey = poisson.electric_field(D, phi_fluct)
         phi = phi_mean[:, None] + phi_fluct
         drho = lbm.density_deviation(self.ft)
         rho = self.rho_ref[:, None] + drho

@@ -78,10 +78,30 @@ def test_manufactured_discrete_solution(nx, ny, kx):
     rho_c = -s * eps
     phi = poisson.solve(rho_c, eps)
     assert np.max(np.abs(phi - phi_star)) < 1e-12 * max(1.0, np.max(np.abs(phi_star)))
-    mean, fl = poisson.solve_split(rho_c, eps)
+    mean, D, fl = poisson.solve_split(rho_c, eps)
     assert np.allclose(mean, A, atol=1e-12)
+    ext = np.concatenate([[2.0 - A[0]], A, [-A[-1]]])
+    assert np.allclose(D, ext[1:] - ext[:-1], atol=1e-12)
     assert np.allclose(fl, B[:, None] * np.cos(2 * np.pi * kx * np.arange(nx) / nx)[None, :],
                        atol=1e-12)
+
+
+@pytest.mark.parametrize("ny", [3, 10, 100, 840])
+def test_mean_mode_flux_form_matches_dense_solve(ny):
+    """The m = 0 solve in flux form equals a dense LAPACK solve of the same
+    3-point system with the electrode ghosts."""
+    rng = np.random.default_rng(15)
+    sbar = -1e-3 * (1.0 + rng.uniform(0, 1, ny))
+    A = -2.0 * np.eye(ny) + np.eye(ny, k=1) + np.eye(ny, k=-1)
+    A[0, 0] = A[-1, -1] = -3.0
+    rhs = sbar.copy()
+    rhs[0] -= 2.0 * 1.0
+    ref = np.linalg.solve(A, rhs)
+    mean, D = poisson.mean_mode(sbar, 1.0, 0.0)
+    # the dense solve's own error grows with the condition number ~ ny^2
+    assert np.max(np.abs(mean - ref)) < 1e-15 * max(ny * ny, 100)
+    ext = np.concatenate([[2.0 - ref[0]], ref, [-ref[-1]]])
+    assert np.allclose(D, ext[1:] - ext[:-1], rtol=1e-9, atol=1e-13)
 
 
 def test_odd_extension_route_of_eq21_25():
@@ -129,8 +149,8 @@ def test_second_order_convergence_to_continuous_solution():
 
 def test_uniform_field_without_charge():
     nx, ny = 10, 7
-    mean, fl = poisson.solve_split(np.zeros((ny, nx)), 3.0)
-    ex, ey = poisson.electric_field(mean, fl)
+    mean, D, fl = poisson.solve_split(np.zeros((ny, nx)), 3.0)
+    ex, ey = poisson.electric_field(D, fl)
     assert np.allclose(ey, 1.0 / ny, rtol=1e-13)
     assert np.allclose(ex, 0.0, atol=1e-17)
     assert np.allclose(mean, 1.0 - (np.arange(ny) + 0.5) / ny, atol=1e-14)
@@ -143,7 +163,8 @@ def test_field_of_a_transverse_mode():
     B = np.sin(np.pi * (np.arange(ny) + 0.5) / ny)
     x = np.arange(nx)
     fl = B[:, None] * np.cos(2 * np.pi * x / nx)[None, :]
-    ex, ey = poisson.electric_field(A, fl)
+    extA = np.concatenate([[2.0 - A[0]], A, [-A[-1]]])
+    ex, ey = poisson.electric_field(extA[1:] - extA[:-1], fl)
     ex_ref = -B[:, None] * (np.cos(2 * np.pi * (x + 1) / nx) - np.cos(2 * np.pi * (x - 1) / nx))[None, :] / 2
     assert np.allclose(ex, ex_ref, atol=1e-15)
     full = A[:, None] + fl
