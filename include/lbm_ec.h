@@ -1,0 +1,171 @@
+/*
+ * lbm_ec.h -- C ABI of the MI355X (gfx950) electroconvection time step.
+ *
+ * The library advances the segregated electroconvection model of Guan &
+ * Novosselov, "Two Relaxation Time Lattice Boltzmann Method Coupled to Fast
+ * Fourier Transform Poisson Solver" (arXiv:1812.05711):
+ *   - two D2Q9 two-relaxation-time lattices, one for the fluid with the
+ *     electric body force -rho_c grad(phi) (section IV.2, Eq. 5, 7, 8, 10,
+ *     12, 13, 15-17) and one for the charge density with the drift velocity
+ *     u - mu_b grad(phi) (Eq. 6, 9, 11, 14, 16-17);
+ *   - coupled every step to a Poisson solve for phi (Eq. 4, 18-25): a DFT
+ *     along the periodic x direction, then one tridiagonal solve in y per
+ *     wavenumber with the electrode potentials as Dirichlet values;
+ *   - electrode and wall conditions of Table I (periodic in x; halfway
+ *     bounce-back of f at both electrodes; rho_c = rho0 at the injector by
+ *     anti-bounce-back of g; zero normal gradient of g at the collector).
+ * The governing groups are those of Eq. 26 (M, T, C, Fe).
+ *
+ * Conventions shared by every entry point
+ *   - Lattice units: dx = dy = dt = 1, electrode gap H = ny, potential drop
+ *     1 (phi = 1 at the injector y = 0, phi = 0 at the collector y = ny),
+ *     fluid density about 1.  Nodes sit at y = j + 1/2, j = 0 .. ny-1, and
+ *     x = 0 .. nx-1 (periodic).
+ *   - All device memory is owned by the caller (allocate it with any
+ *     allocator, e.g. PyTorch); the library never allocates or frees device
+ *     memory.  A handle owns only host memory.
+ *   - Work is enqueued asynchronously on the caller's HIP stream given at
+ *     creation; only lbm_ec_create and lbm_ec_stats wait for the stream.
+ *   - Every int-returning call returns LBM_EC_OK (0) or an error code and
+ *     leaves a message for lbm_ec_last_error() (thread-local).
+ *   - Calls on one handle must not run concurrently from several threads.
+ */
+#ifndef LBM_EC_H
+#define LBM_EC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+enum {
+  LBM_EC_OK = 0,
+  LBM_EC_EINVAL = 1,   /* invalid argument or parameter set */
+  LBM_EC_ENOMEM = 2,   /* workspace smaller than lbm_ec_workspace_bytes() */
+  LBM_EC_EHIP = 3,     /* a HIP runtime call or kernel launch failed */
+  LBM_EC_EUNSTABLE = 4,/* the health check found non-finite or negative density */
+  LBM_EC_EBUSY = 5     /* no free slot or budget (batch API) */
+};
+
+/* storage precision of the populations */
+enum {
+  LBM_EC_FP64 = 0,     /* FP64 storage and arithmetic everywhere */
+  LBM_EC_FP32_DEV = 1  /* FP32 deviations from the hydrostatic reference rows;
+                          FP64 for the x-mean (m = 0) Poisson mode and the
+                          reductions */
+};
+
+/* initial state */
+enum {
+  LBM_EC_INIT_NOISE = 0, /* closed-form hydrostatic state (Eq. 27-28) times
+                            (1 + noise_amp * xi), xi uniform on [-1, 1) from
+                            SplitMix64 output k = j*nx + x, seeded with
+                            seed + instance_id */
+  LBM_EC_INIT_EQ29 = 1,  /* hydrostatic state plus the velocity perturbation
+                            of Eq. 29 (section V.2) */
+  LBM_EC_INIT_REST = 2   /* rho = 1, u = 0, no charge (flow tests) */
+};
+
+/* which TRT rate of the charge lattice carries the diffusivity D_c */
+enum {
+  LBM_EC_RATES_ANTISYMMETRIC = 0, /* D_c = cs2 (1/w_g- - 1/2); Lambda_g sets
+                                     w_g+.  Gives the charge diffusivity K/Fe. */
+  LBM_EC_RATES_SYMMETRIC = 1      /* the labels printed in Eq. 16:
+                                     D_c = cs2 (1/w_g+ - 1/2) */
+};
+
+/* Parameters of one simulation (Eq. 16-17, Eq. 26). */
+typedef struct {
+  int32_t nx, ny;       /* grid; nx >= 1, ny >= 3 */
+  double T, C, M, Fe;   /* electric Rayleigh number, injection level, mobility
+                           ratio, inverse charge diffusivity (Eq. 26) */
+  double tau_plus;      /* fluid symmetric relaxation time (> 1/2); sets the
+                           viscosity nu = (tau_plus - 1/2)/3, from which the
+                           mobility K = nu T / M^2, permittivity (M K)^2,
+                           injected charge C (M K)^2 / ny^2 and D_c = K / Fe */
+  double Lambda;        /* fluid TRT product of Eq. 17 (> 0) */
+  double Lambda_g;      /* charge TRT product of Eq. 17 (> 0) */
+  int32_t precision;    /* LBM_EC_FP64 or LBM_EC_FP32_DEV */
+  int32_t init_mode;    /* LBM_EC_INIT_* */
+  double noise_amp;     /* relative charge noise amplitude (INIT_NOISE) */
+  uint64_t seed;        /* noise generator seed */
+  int32_t instance_id;  /* added to the seed */
+  int32_t charge_rates; /* LBM_EC_RATES_* */
+  double body_force_x;  /* uniform x body force density (flow tests; 0 otherwise) */
+} lbm_ec_params;
+
+typedef struct lbm_ec lbm_ec_t;
+
+/* Fills *p with the defaults: 122 x 100, T = 200, C = 10, M = 10, Fe = 4000,
+ * tau_plus = 0.8, Lambda = 1/4, Lambda_g = 1e-6, FP64, INIT_NOISE,
+ * noise_amp = 1e-3, seed = 181205711.  Returns EINVAL if p is NULL. */
+int lbm_ec_params_default(lbm_ec_params* p);
+
+/* Checks a parameter set (see the field comments; also nx within the
+ * x-transform limit of the chosen precision).  Returns OK or EINVAL. */
+int lbm_ec_validate(const lbm_ec_params* p);
+
+/* Device workspace bytes needed by lbm_ec_create for *p (0 if invalid). */
+size_t lbm_ec_workspace_bytes(const lbm_ec_params* p);
+
+/* Creates a simulation in the caller's device workspace d_ws (ws_bytes
+ * bytes, 256-byte aligned, on the current HIP device) and enqueues the
+ * initial state on hip_stream (a hipStream_t; NULL means the null stream).
+ * The initial state is step 0: the pre-collision populations are set to
+ * their equilibria for the chosen init mode, the Poisson problem is solved
+ * for them, and their first collision is done, as the pull-streaming time
+ * loop expects.  Waits for the stream once.  The workspace must stay
+ * allocated and untouched by the caller until lbm_ec_destroy.
+ * Errors: EINVAL (bad parameters or NULL pointers), ENOMEM (ws_bytes too
+ * small or misaligned), EHIP. */
+int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes,
+                  void* hip_stream, lbm_ec_t** out);
+
+/* Enqueues n >= 0 time steps (section IV: charge density, Poisson solve,
+ * field, TRT collision and streaming of both lattices).  Asynchronous. */
+int lbm_ec_step(lbm_ec_t* h, int64_t n);
+
+/* Number of steps taken since creation. */
+int64_t lbm_ec_steps_done(const lbm_ec_t* h);
+
+/* Enqueues the conversion of the current state (after lbm_ec_steps_done
+ * steps) into nondimensional FP64 fields, each a device array of ny*nx
+ * doubles in row-major [y][x] order:
+ *   rho   -- fluid density (lattice units, about 1)
+ *   ux,uy -- velocity in units of u0 = K / H
+ *   rho_c -- charge density in units of eps / H^2 (C at the injector)
+ *   phi   -- potential in units of the applied drop (1 at the injector)
+ * Any pointer may be NULL to skip that field.  Asynchronous. */
+int lbm_ec_fields(lbm_ec_t* h, double* rho, double* ux, double* uy,
+                  double* rho_c, double* phi);
+
+/* Solves the Poisson problem of Eq. 4 and 18-25 for a given charge density:
+ * d_rho_c and d_phi are device arrays of ny*nx doubles, [y][x], in the
+ * nondimensional units of lbm_ec_fields.  Uses the handle's transforms and
+ * scratch (it overwrites the handle's potential, so call it between steps
+ * only for testing).  Asynchronous. */
+int lbm_ec_poisson(lbm_ec_t* h, const double* d_rho_c, double* d_phi);
+
+/* Global diagnostics of the current state, computed in FP64 on the device
+ * and copied to host memory out[8] (waits for the stream):
+ *   out[0] steps done, out[1] sum of (rho - 1) over nodes, out[2] sum of
+ *   rho_c (lattice units), out[3] rms of u_y (lattice units), out[4] max of
+ *   |u| (lattice units), out[5] min rho_c, out[6] number of non-finite or
+ *   non-positive-density nodes, out[7] max |E_x| (lattice units).
+ * Returns EUNSTABLE (after filling out) if out[6] > 0. */
+int lbm_ec_stats(lbm_ec_t* h, double* out);
+
+/* Releases the handle (host memory only; the caller frees the workspace). */
+void lbm_ec_destroy(lbm_ec_t* h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* lbm_ec_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_EC_H */

@@ -1,0 +1,450 @@
+// Host side of the library: parameter mapping, reference rows, transform
+// plans, workspace layout, the time loop and the C ABI of include/lbm_ec.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_ec.h"
+#include "ec_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define EC_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(LBM_EC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Largest x transform the LDS budget of one workgroup allows (two complex
+// buffers of n elements within 64 KiB).
+int max_nx(int precision) { return precision == LBM_EC_FP64 ? 2048 : 4096; }
+
+// v rounded to `bits` significant bits, ties to even.
+double round_bits(double v, int bits) {
+  if (v == 0.0 || !std::isfinite(v)) return v;
+  int e;
+  const double m = std::frexp(v, &e);
+  return std::ldexp(std::nearbyint(std::ldexp(m, bits)), e - bits);
+}
+
+// Field at the injector of the closed-form hydrostatic state (Eq. 27-28):
+// the root E0 of [(E0^2 + 2 C E0)^(3/2) - E0^3] / (3 C E0) = 1, by bisection.
+double field_at_injector(double C) {
+  if (C == 0.0) return 1.0;
+  auto drop = [C](double e0) { return (std::pow(e0 * e0 + 2.0 * C * e0, 1.5) - std::pow(e0, 3.0)) / (3.0 * C * e0) - 1.0; };
+  double lo = 0.0, hi = 1.0;
+  for (;;) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (drop(mid) < 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+ec::FftPlan make_plan(int n) {
+  ec::FftPlan p{};
+  p.n = n;
+  p.nr = 0;
+  int m = n;
+  const int pref[5] = {8, 4, 2, 3, 5};
+  for (int r : pref)
+    while (m % r == 0 && p.nr < ec::kMaxRadices) {
+      p.r[p.nr++] = r;
+      m /= r;
+    }
+  for (int q = 7; m > 1 && p.nr < ec::kMaxRadices; q += 2)
+    while (m % q == 0) {
+      p.r[p.nr++] = q;
+      m /= q;
+    }
+  return p;
+}
+
+struct Layout {
+  int P, M, MP;
+  size_t tsize;
+  size_t off_f[2], off_g[2], off_phi, off_spec, off_cp, off_tw, off_rows, off_rowsd, off_dmean, off_mom,
+      off_stats, total;
+};
+
+Layout make_layout(const lbm_ec_params& p) {
+  Layout L{};
+  L.tsize = p.precision == LBM_EC_FP64 ? 8 : 4;
+  const int elems = (int)(256 / L.tsize);  // pitch multiple of 256 bytes
+  L.P = (p.nx + elems - 1) / elems * elems;
+  L.M = p.nx / 2 + 1;
+  L.MP = (L.M + elems - 1) / elems * elems;
+  const size_t ny = (size_t)p.ny, nx = (size_t)p.nx;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t pop = 9 * ny * L.P * L.tsize;
+  L.off_f[0] = take(pop);
+  L.off_f[1] = take(pop);
+  L.off_g[0] = take(pop);
+  L.off_g[1] = take(pop);
+  L.off_phi = take(ny * L.P * L.tsize);
+  L.off_spec = take(ny * L.MP * 2 * L.tsize);
+  L.off_cp = take(ny * L.MP * L.tsize);
+  L.off_tw = take(nx * 2 * L.tsize);
+  L.off_rows = take(ec::ROW_COUNT * ny * L.tsize);
+  L.off_rowsd = take(ec::ROWD_COUNT * ny * 8);
+  L.off_dmean = take((ny + 1) * 8);
+  L.off_mom = take(4 * ny * nx * 8);
+  L.off_stats = take(16 * 8);
+  L.total = o;
+  return L;
+}
+
+int validate(const lbm_ec_params* p) {
+  if (!p) return fail(LBM_EC_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 3) return fail(LBM_EC_EINVAL, "grid must have nx >= 1 and ny >= 3");
+  if (p->precision != LBM_EC_FP64 && p->precision != LBM_EC_FP32_DEV)
+    return fail(LBM_EC_EINVAL, "unknown precision");
+  if (p->nx > max_nx(p->precision))
+    return fail(LBM_EC_EINVAL, "nx exceeds the x-transform limit (" + std::to_string(max_nx(p->precision)) +
+                                   ") of this precision");
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_EC_EINVAL, "grid too large");
+  if (!(p->tau_plus > 0.5) || !std::isfinite(p->tau_plus)) return fail(LBM_EC_EINVAL, "tau_plus must exceed 1/2");
+  if (!(p->Lambda > 0) || !(p->Lambda_g > 0)) return fail(LBM_EC_EINVAL, "Lambda and Lambda_g must be positive");
+  if (!(p->T > 0) || !(p->M > 0) || !(p->Fe > 0) || !(p->C >= 0) || !std::isfinite(p->T) ||
+      !std::isfinite(p->C) || !std::isfinite(p->M) || !std::isfinite(p->Fe))
+    return fail(LBM_EC_EINVAL, "T, M, Fe must be positive and finite, C non-negative");
+  if (p->init_mode < 0 || p->init_mode > 2) return fail(LBM_EC_EINVAL, "unknown init_mode");
+  if (p->charge_rates != LBM_EC_RATES_ANTISYMMETRIC && p->charge_rates != LBM_EC_RATES_SYMMETRIC)
+    return fail(LBM_EC_EINVAL, "unknown charge_rates");
+  if (!std::isfinite(p->noise_amp) || !std::isfinite(p->body_force_x))
+    return fail(LBM_EC_EINVAL, "noise_amp and body_force_x must be finite");
+  return LBM_EC_OK;
+}
+
+}  // namespace
+
+struct lbm_ec {
+  lbm_ec_params p;
+  Layout L;
+  ec::Consts c;
+  ec::Bufs b;
+  ec::FftPlan plan;
+  hipStream_t s;
+  int cur;  // buffer holding the latest post-collision populations
+  int64_t steps;
+  bool fp32;
+};
+
+namespace {
+
+// Lattice constants (Eq. 16-17, Eq. 26 with rho = 1, dphi0 = 1, H = ny) and
+// all tables, written into host vectors then copied to the device.
+template <typename T>
+int setup(lbm_ec* h, unsigned char* ws) {
+  const lbm_ec_params& p = h->p;
+  const Layout& L = h->L;
+  const int nx = p.nx, ny = p.ny;
+  const double H = (double)ny;
+  const double nu = kCs2 * (p.tau_plus - 0.5);
+  const double K = nu * p.T / (p.M * p.M);
+  const double eps = (p.M * K) * (p.M * K);
+  const double rho0 = p.C * eps / (H * H);
+  const double Dc = K / p.Fe;
+  const double tau_m = 0.5 + p.Lambda / (p.tau_plus - 0.5);
+  const double tau_gd = 0.5 + Dc / kCs2;
+  const double tau_go = 0.5 + p.Lambda_g / (tau_gd - 0.5);
+  double tau_gp, tau_gm;
+  if (p.charge_rates == LBM_EC_RATES_ANTISYMMETRIC) {
+    tau_gp = tau_go;
+    tau_gm = tau_gd;
+  } else {
+    tau_gp = tau_gd;
+    tau_gm = tau_go;
+  }
+  ec::Consts& c = h->c;
+  c.nx = nx;
+  c.ny = ny;
+  c.P = L.P;
+  c.M = L.M;
+  c.MP = L.MP;
+  c.wp = 1.0 / p.tau_plus;
+  c.wm = 1.0 / tau_m;
+  c.wgp = 1.0 / tau_gp;
+  c.wgm = 1.0 / tau_gm;
+  c.K = K;
+  c.eps = eps;
+  c.bx = p.body_force_x;
+  c.H = H;
+  c.u0 = K / H;
+  c.init_mode = p.init_mode;
+  c.noise_amp = p.noise_amp;
+  c.seed = p.seed + (uint64_t)(int64_t)p.instance_id;
+
+  // reference rows: closed-form hydrostatic charge profile r(j) and the
+  // linear density profile balancing its uniform force; rounded so that
+  // w_i times them, and their differences between rows, are exact in T.
+  const bool rest = p.init_mode == LBM_EC_INIT_REST;
+  const int bits = sizeof(T) == 8 ? 40 : 18;
+  const double e0 = field_at_injector(p.C);
+  std::vector<double> rc_closed(ny, 0.0);
+  double s_ref = 0.0;
+  if (!rest) {
+    for (int j = 0; j < ny; ++j) {
+      const double y = ((double)j + 0.5) / (double)ny;
+      double rc_nd = 0.0;
+      if (p.C != 0.0) {
+        const double e2 = e0 * e0 + 2.0 * p.C * e0 * y;
+        rc_nd = p.C * e0 / std::sqrt(e2);
+      }
+      rc_closed[j] = eps / (H * H) * rc_nd;
+    }
+    const double F0 = eps * p.C * e0 / std::pow(H, 3.0);
+    s_ref = 3.0 * F0;
+  }
+  s_ref = 36.0 * round_bits(s_ref / 36.0, bits);
+  std::vector<double> q(ny), rho_ref(ny);
+  for (int j = 0; j < ny; ++j) {
+    q[j] = round_bits(rc_closed[j] / 36.0, bits);
+    rho_ref[j] = 1.0 + s_ref * (((double)j + 0.5) - 0.5 * H);
+  }
+  const double wa = 1.0 / 9.0, wd = 1.0 / 36.0;
+  c.f_up_axis = -wa * s_ref;
+  c.f_up_diag = -wd * s_ref;
+  c.f_dn_axis = wa * s_ref;
+  c.f_dn_diag = wd * s_ref;
+  // R_axis = 4 q, R_diag = q (36 w_i is exactly 4 and 1)
+  c.g_abb_axis = 2.0 * (wa * rho0 - 4.0 * q[0]);
+  c.g_abb_diag = 2.0 * (wd * rho0 - 1.0 * q[0]);
+
+  std::vector<T> rows((size_t)ec::ROW_COUNT * ny, T(0));
+  std::vector<double> rowsd((size_t)ec::ROWD_COUNT * ny, 0.0);
+  for (int j = 0; j < ny; ++j) {
+    rows[ec::ROW_RHO_REF * ny + j] = (T)rho_ref[j];
+    rows[ec::ROW_R * ny + j] = (T)(36.0 * q[j]);
+    if (j > 0) {
+      rows[ec::ROW_DG_UP_AXIS * ny + j] = (T)(4.0 * q[j - 1] - 4.0 * q[j]);
+      rows[ec::ROW_DG_UP_DIAG * ny + j] = (T)(q[j - 1] - q[j]);
+    }
+    if (j < ny - 1) {
+      rows[ec::ROW_DG_DN_AXIS * ny + j] = (T)(4.0 * q[j + 1] - 4.0 * q[j]);
+      rows[ec::ROW_DG_DN_DIAG * ny + j] = (T)(q[j + 1] - q[j]);
+    }
+    rowsd[ec::ROWD_RHO_REF * ny + j] = rho_ref[j];
+    rowsd[ec::ROWD_R * ny + j] = 36.0 * q[j];
+    rowsd[ec::ROWD_RC_CLOSED * ny + j] = rc_closed[j];
+  }
+
+  // elimination factors of the per-wavenumber systems (m >= 1)
+  const int M = L.M, MP = L.MP;
+  std::vector<T> cp((size_t)ny * MP, T(0));
+  for (int m = 1; m < M; ++m) {
+    const int mf = std::min(m, nx - m);
+    const double kap = 2.0 * M_PI * (double)mf / (double)nx;
+    const double b = -(2.0 + kap * kap);
+    double prev = 0.0;
+    for (int j = 0; j < ny; ++j) {
+      const double diag = b - ((j == 0 || j == ny - 1) ? 1.0 : 0.0);
+      const double cpj = j == 0 ? 1.0 / diag : 1.0 / (diag - prev);
+      cp[(size_t)j * MP + m] = (T)cpj;
+      prev = cpj;
+    }
+  }
+  // twiddles exp(-2 pi i k / nx)
+  std::vector<T> tw(2 * (size_t)nx);
+  for (int k = 0; k < nx; ++k) {
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)nx;
+    tw[2 * k] = (T)cosl(a);
+    tw[2 * k + 1] = (T)(-sinl(a));
+  }
+  EC_HIP(hipMemcpyAsync(h->b.rows, rows.data(), rows.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.rowsd, rowsd.data(), rowsd.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.cp, cp.data(), cp.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipMemsetAsync(ws + L.off_spec, 0, (size_t)ny * MP * 2 * sizeof(T), h->s));
+  EC_HIP(hipMemsetAsync(ws + L.off_phi, 0, (size_t)ny * L.P * sizeof(T), h->s));
+  EC_HIP(hipMemsetAsync(ws + L.off_mom, 0, 4 * (size_t)ny * nx * 8, h->s));
+  EC_HIP(hipStreamSynchronize(h->s));  // the host vectors go out of scope
+  return LBM_EC_OK;
+}
+
+template <typename T>
+int poisson_chain(lbm_ec* h, int mode, int src) {
+  EC_HIP(ec::launch_forward<T>(h->c, h->b, h->plan, mode, src, h->s));
+  EC_HIP(ec::launch_mean_mode<T>(h->c, h->b, h->s));
+  EC_HIP(ec::launch_tridiag<T>(h->c, h->b, h->s));
+  EC_HIP(ec::launch_inverse<T>(h->c, h->b, h->plan, h->s));
+  return LBM_EC_OK;
+}
+
+template <typename T>
+int init_state(lbm_ec* h) {
+  int rc;
+  // initial charge, its potential, the equilibria into buffer 1
+  EC_HIP(ec::launch_init_charge<T>(h->c, h->b, h->s));
+  if ((rc = poisson_chain<T>(h, 2, 0))) return rc;
+  EC_HIP(ec::launch_init_populations<T>(h->c, h->b, 1, h->s));
+  // step 0: charge of the initial populations, Poisson, first collision
+  // (no streaming) into buffer 0, with the moments of state 0
+  if ((rc = poisson_chain<T>(h, 1, 1))) return rc;
+  EC_HIP(ec::launch_collide<T>(h->c, h->b, false, true, 1, 0, h->s));
+  h->cur = 0;
+  h->steps = 0;
+  return LBM_EC_OK;
+}
+
+template <typename T>
+int run_steps(lbm_ec* h, int64_t n) {
+  int rc;
+  for (int64_t k = 0; k < n; ++k) {
+    const int src = h->cur, dst = 1 - h->cur;
+    if ((rc = poisson_chain<T>(h, 0, src))) return rc;
+    EC_HIP(ec::launch_collide<T>(h->c, h->b, true, k == n - 1, src, dst, h->s));
+    h->cur = dst;
+    h->steps += 1;
+  }
+  return LBM_EC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_ec_params_default(lbm_ec_params* p) {
+  if (!p) return fail(LBM_EC_EINVAL, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->nx = 122;
+  p->ny = 100;
+  p->T = 200.0;
+  p->C = 10.0;
+  p->M = 10.0;
+  p->Fe = 4000.0;
+  p->tau_plus = 0.8;
+  p->Lambda = 0.25;
+  p->Lambda_g = 1e-6;
+  p->precision = LBM_EC_FP64;
+  p->init_mode = LBM_EC_INIT_NOISE;
+  p->noise_amp = 1e-3;
+  p->seed = 181205711ull;
+  p->instance_id = 0;
+  p->charge_rates = LBM_EC_RATES_ANTISYMMETRIC;
+  p->body_force_x = 0.0;
+  return LBM_EC_OK;
+}
+
+int lbm_ec_validate(const lbm_ec_params* p) { return validate(p); }
+
+size_t lbm_ec_workspace_bytes(const lbm_ec_params* p) {
+  if (validate(p) != LBM_EC_OK) return 0;
+  return make_layout(*p).total;
+}
+
+int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip_stream, lbm_ec_t** out) {
+  g_err.clear();
+  if (!out) return fail(LBM_EC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!d_ws) return fail(LBM_EC_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(*p);
+  if (ws_bytes < L.total)
+    return fail(LBM_EC_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  if (((uintptr_t)d_ws) % kAlign) return fail(LBM_EC_ENOMEM, "workspace must be 256-byte aligned");
+  lbm_ec* h = new lbm_ec();
+  h->p = *p;
+  h->L = L;
+  h->s = (hipStream_t)hip_stream;
+  h->fp32 = p->precision == LBM_EC_FP32_DEV;
+  h->plan = make_plan(p->nx);
+  unsigned char* ws = (unsigned char*)d_ws;
+  h->b.f[0] = ws + L.off_f[0];
+  h->b.f[1] = ws + L.off_f[1];
+  h->b.g[0] = ws + L.off_g[0];
+  h->b.g[1] = ws + L.off_g[1];
+  h->b.phi = ws + L.off_phi;
+  h->b.spec = ws + L.off_spec;
+  h->b.cp = ws + L.off_cp;
+  h->b.tw = ws + L.off_tw;
+  h->b.rows = ws + L.off_rows;
+  h->b.rowsd = (double*)(ws + L.off_rowsd);
+  h->b.dmean = (double*)(ws + L.off_dmean);
+  h->b.mom = (double*)(ws + L.off_mom);
+  h->b.stats = (double*)(ws + L.off_stats);
+  rc = h->fp32 ? setup<float>(h, ws) : setup<double>(h, ws);
+  if (!rc) rc = h->fp32 ? init_state<float>(h) : init_state<double>(h);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(h->s);
+    if (e != hipSuccess) rc = fail(LBM_EC_EHIP, std::string("initial state: ") + hipGetErrorString(e));
+  }
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LBM_EC_OK;
+}
+
+int lbm_ec_step(lbm_ec_t* h, int64_t n) {
+  if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
+  if (n < 0) return fail(LBM_EC_EINVAL, "negative step count");
+  return h->fp32 ? run_steps<float>(h, n) : run_steps<double>(h, n);
+}
+
+int64_t lbm_ec_steps_done(const lbm_ec_t* h) { return h ? h->steps : -1; }
+
+int lbm_ec_fields(lbm_ec_t* h, double* rho, double* ux, double* uy, double* rho_c, double* phi) {
+  if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
+  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, rho, ux, uy, rho_c, phi, h->s)
+                 : ec::launch_fields<double>(h->c, h->b, rho, ux, uy, rho_c, phi, h->s));
+  return LBM_EC_OK;
+}
+
+int lbm_ec_poisson(lbm_ec_t* h, const double* d_rho_c, double* d_phi) {
+  if (!h || !d_rho_c || !d_phi) return fail(LBM_EC_EINVAL, "NULL argument");
+  int rc;
+  if (h->fp32) {
+    EC_HIP(ec::launch_charge_in<float>(h->c, h->b, d_rho_c, h->s));
+    if ((rc = poisson_chain<float>(h, 2, 0))) return rc;
+    EC_HIP(ec::launch_fields<float>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, d_phi, h->s));
+  } else {
+    EC_HIP(ec::launch_charge_in<double>(h->c, h->b, d_rho_c, h->s));
+    if ((rc = poisson_chain<double>(h, 2, 0))) return rc;
+    EC_HIP(ec::launch_fields<double>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, d_phi, h->s));
+  }
+  return LBM_EC_OK;
+}
+
+int lbm_ec_stats(lbm_ec_t* h, double* out) {
+  if (!h || !out) return fail(LBM_EC_EINVAL, "NULL argument");
+  EC_HIP(h->fp32 ? ec::launch_stats<float>(h->c, h->b, h->s) : ec::launch_stats<double>(h->c, h->b, h->s));
+  double tmp[16];
+  EC_HIP(hipMemcpyAsync(tmp, h->b.stats, sizeof(tmp), hipMemcpyDeviceToHost, h->s));
+  EC_HIP(hipStreamSynchronize(h->s));
+  tmp[0] = (double)h->steps;
+  for (int i = 0; i < 8; ++i) out[i] = tmp[i];
+  if (tmp[6] > 0) return fail(LBM_EC_EUNSTABLE, "non-finite values or non-positive density in the state");
+  return LBM_EC_OK;
+}
+
+void lbm_ec_destroy(lbm_ec_t* h) { delete h; }
+
+const char* lbm_ec_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

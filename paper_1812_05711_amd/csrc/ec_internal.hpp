@@ -1,0 +1,113 @@
+// Internal declarations shared by the host side (ec_capi.hip) and the
+// kernels (ec_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ec {
+
+// Mixed-radix plan of one x transform of length n (radices in pass order).
+constexpr int kMaxRadices = 32;
+struct FftPlan {
+  int n;
+  int nr;
+  int r[kMaxRadices];
+};
+
+// Scalar constants of one instance, in lattice units (see the public header
+// for the unit conventions).  Kernels convert to their storage type.
+struct Consts {
+  int nx, ny;  // grid
+  int P;       // row pitch of node arrays, elements
+  int M;       // number of non-negative x wavenumbers, nx/2 + 1
+  int MP;      // row pitch of spectral arrays, elements
+  double wp, wm, wgp, wgm;  // TRT rates: fluid +/-, charge +/-
+  double K;                 // ion mobility
+  double eps;               // permittivity
+  double bx;                // body force density along x
+  double H;                 // electrode gap (= ny)
+  double u0;                // velocity unit K / H
+  // re-reference of f on y-streaming: arrivals from the row below
+  // (c_iy = +1) and from the row above (c_iy = -1), axis / diagonal weights
+  double f_up_axis, f_up_diag, f_dn_axis, f_dn_diag;
+  // injector anti-bounce-back constants 2 (w_i rho0 - R_i(0)) on deviations
+  double g_abb_axis, g_abb_diag;
+  // initial state
+  int init_mode;
+  double noise_amp;
+  uint64_t seed;
+};
+
+// Per-row tables in the storage type (index k * ny + j).
+enum RowTable {
+  ROW_RHO_REF = 0,   // hydrostatic reference density rho_ref(j)
+  ROW_R = 1,         // reference charge row r(j)
+  ROW_DG_UP_AXIS,    // R_axis(j-1) - R_axis(j): g arriving from below
+  ROW_DG_UP_DIAG,
+  ROW_DG_DN_AXIS,    // R_axis(j+1) - R_axis(j): g arriving from above
+  ROW_DG_DN_DIAG,
+  ROW_COUNT
+};
+
+// Per-row tables in FP64 (index k * ny + j).
+enum RowTableD {
+  ROWD_RHO_REF = 0,  // rho_ref(j)
+  ROWD_R = 1,        // r(j)
+  ROWD_RC_CLOSED,    // closed-form charge profile (initial state)
+  ROWD_DCSUM,        // sum over x of the charge deviation (written each step)
+  ROWD_EYM,          // x-mean field E_y(j) (written each step)
+  ROWD_PHIM,         // x-mean potential (written each step)
+  ROWD_COUNT
+};
+
+// Device pointers of one instance inside the caller's workspace.
+struct Bufs {
+  void* f[2];    // [9][ny][P] populations (deviations), ping-pong
+  void* g[2];
+  void* phi;     // [ny][P] potential fluctuation (m >= 1 modes)
+  void* spec;    // [ny][MP] complex spectrum (forward, solved in place)
+  void* cp;      // [ny][MP] Thomas elimination factors, per wavenumber
+  void* tw;      // [nx] complex twiddles exp(-2 pi i k / nx)
+  void* rows;    // ROW_COUNT x [ny]
+  double* rowsd; // ROWD_COUNT x [ny]
+  double* dmean; // [ny + 1] x-mean row differences D(-1) .. D(ny-1)
+  double* mom;   // [4][ny][nx] emitted moments: rho - rho_ref, ux, uy, rho_c - r
+  double* stats; // [16]
+};
+
+// Kernel launchers (ec_kernels.hip).  All enqueue on `s` and return the
+// launch status.
+template <typename T>
+hipError_t launch_init_charge(const Consts& c, const Bufs& b, hipStream_t s);
+template <typename T>
+hipError_t launch_init_populations(const Consts& c, const Bufs& b, int dst, hipStream_t s);
+// mode 0: pull-gather from post-collision g[src]; 1: local sum of g[src];
+// 2: read the charge deviation field held in b.mom (plane 3)
+template <typename T>
+hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_mean_mode(const Consts& c, const Bufs& b, hipStream_t s);
+template <typename T>
+hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s);
+template <typename T>
+hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, hipStream_t s);
+template <typename T>
+hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_fields(const Consts& c, const Bufs& b, double* rho, double* ux, double* uy,
+                         double* rho_c, double* phi, hipStream_t s);
+template <typename T>
+hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_nd, hipStream_t s);
+template <typename T>
+hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s);
+
+// LDS bytes the x transforms need for length n.
+template <typename T>
+size_t fft_lds_bytes(int n);
+
+}  // namespace ec

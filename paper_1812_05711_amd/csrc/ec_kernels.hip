@@ -1,0 +1,894 @@
+// Device code of the coupled TRT-LBM / FFT-Poisson electroconvection step
+// for gfx950 (wave64).  Every kernel is templated on the storage type T
+// (double, or float for the FP32-deviation mode); quantities that the
+// precision policy keeps in FP64 (the x-mean Poisson mode, its field, the
+// reductions) are double in both modes.
+//
+// Data layout (row-major, x fastest):
+//   populations  [9][ny][P] deviations from the hydrostatic reference rows:
+//                f_i - w_i rho_ref(y) and g_i - R_i(y), R_i = w_i r(y)
+//   potential    phi fluctuation [ny][P] (the m >= 1 modes) plus the x-mean
+//                row in FP64
+//   spectrum     [ny][MP] complex, m = 0 .. nx/2 (one row per y)
+#include "ec_internal.hpp"
+
+namespace ec {
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct C2 {
+  T re, im;
+};
+template <typename T>
+__device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cscale(C2<T> a, T s) {
+  return {a.re * s, a.im * s};
+}
+// multiply by s*i, s = -1 for the forward transform, +1 for the inverse
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> rot(C2<T> a) {
+  return INV ? C2<T>{-a.im, a.re} : C2<T>{a.im, -a.re};
+}
+
+// ------------------------------------------------- small DFTs in registers
+// y_q = sum_r v_r exp(s 2 pi i r q / R), s = -1 forward / +1 inverse.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(C2<T>* v) {
+  C2<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(C2<T>& a0, C2<T>& a1, C2<T>& a2, C2<T>& a3) {
+  C2<T> t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  C2<T> t2 = cadd(a1, a3), t3 = rot<T, INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a1 = cadd(t1, t3);
+  a2 = csub(t0, t2);
+  a3 = csub(t1, t3);
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(C2<T>* v) {
+  const T h = T(0.86602540378443864676);  // sqrt(3)/2
+  C2<T> t = cadd(v[1], v[2]);
+  C2<T> d = csub(v[1], v[2]);
+  C2<T> y0 = cadd(v[0], t);
+  C2<T> m = {v[0].re - T(0.5) * t.re, v[0].im - T(0.5) * t.im};
+  C2<T> k = rot<T, INV>(cscale(d, h));
+  v[0] = y0;
+  v[1] = cadd(m, k);
+  v[2] = csub(m, k);
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft5(C2<T>* v) {
+  const T c1 = T(0.30901699437494742410);   // cos(2 pi / 5)
+  const T c2 = T(-0.80901699437494742410);  // cos(4 pi / 5)
+  const T s1 = T(0.95105651629515357212);   // sin(2 pi / 5)
+  const T s2 = T(0.58778525229247312917);   // sin(4 pi / 5)
+  C2<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  C2<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  C2<T> y0 = cadd(v[0], cadd(t1, t2));
+  C2<T> b1 = {v[0].re + c1 * t1.re + c2 * t2.re, v[0].im + c1 * t1.im + c2 * t2.im};
+  C2<T> b2 = {v[0].re + c2 * t1.re + c1 * t2.re, v[0].im + c2 * t1.im + c1 * t2.im};
+  C2<T> e1 = rot<T, INV>(C2<T>{s1 * t3.re + s2 * t4.re, s1 * t3.im + s2 * t4.im});
+  C2<T> e2 = rot<T, INV>(C2<T>{s2 * t3.re - s1 * t4.re, s2 * t3.im - s1 * t4.im});
+  v[0] = y0;
+  v[1] = cadd(b1, e1);
+  v[4] = csub(b1, e1);
+  v[2] = cadd(b2, e2);
+  v[3] = csub(b2, e2);
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(C2<T>* v) {
+  const T r = T(0.70710678118654752440);
+  C2<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C2<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<T, INV>(e0, e1, e2, e3);
+  dft4<T, INV>(o0, o1, o2, o3);
+  // o_q *= exp(s 2 pi i q / 8)
+  const T sg = INV ? T(1) : T(-1);
+  o1 = cmul(o1, C2<T>{r, sg * r});
+  o2 = rot<T, INV>(o2);
+  o3 = cmul(o3, C2<T>{-r, sg * r});
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+// One Stockham autosort pass of radix R (R in {2,3,4,5,8}) from src to dst:
+// butterfly t reads src[t + r N/R] (r = 0..R-1) with the pre-twiddles
+// exp(s 2 pi i r k / (Ns R)), k = t mod Ns, and writes its R outputs to
+// dst[(t / Ns) Ns R + k + q Ns].  Ns is the product of the radices of the
+// earlier passes; the last pass leaves natural order.
+template <typename T, bool INV, int R>
+__device__ __forceinline__ void stockham_pass(const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
+                                              int N, int Ns, const C2<T>* __restrict__ tw) {
+  const int stride = N / R;
+  const int twstep = N / (Ns * R);
+  for (int t = threadIdx.x; t < stride; t += blockDim.x) {
+    const int k = t % Ns;
+    const int e = k * twstep;
+    C2<T> v[R];
+    v[0] = src[t];
+    int idx = e;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      C2<T> w = tw[idx];
+      if (INV) w.im = -w.im;
+      v[r] = cmul(src[t + r * stride], w);
+      idx += e;
+      if (idx >= N) idx -= N;
+    }
+    if constexpr (R == 2) dft2<T, INV>(v);
+    if constexpr (R == 3) dft3<T, INV>(v);
+    if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    if constexpr (R == 5) dft5<T, INV>(v);
+    if constexpr (R == 8) dft8<T, INV>(v);
+    const int base = (t / Ns) * Ns * R + k;
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
+  }
+}
+
+// Pass of any other radix R: one thread per output (q, t), a direct DFT of
+// the R inputs with the combined twiddle exp(s 2 pi i r (k N/(Ns R) + q N/R) / N).
+template <typename T, bool INV>
+__device__ __forceinline__ void generic_pass(const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
+                                             int N, int Ns, int R, const C2<T>* __restrict__ tw) {
+  const int stride = N / R;
+  const int twstep = N / (Ns * R);
+  for (int o = threadIdx.x; o < N; o += blockDim.x) {
+    const int q = o / stride;
+    const int t = o - q * stride;
+    const int k = t % Ns;
+    const int e = (k * twstep + q * stride) % N;
+    C2<T> acc = src[t];
+    int idx = e;
+    for (int r = 1; r < R; ++r) {
+      C2<T> w = tw[idx];
+      if (INV) w.im = -w.im;
+      acc = cadd(acc, cmul(src[t + r * stride], w));
+      idx += e;
+      if (idx >= N) idx -= N;
+    }
+    dst[(t / Ns) * Ns * R + k + q * Ns] = acc;
+  }
+}
+
+// Complex transform of length pl.n held in LDS buffer a (b is scratch of the
+// same size).  Returns the buffer that holds the result.  Unnormalised:
+// forward uses exp(-2 pi i m x / N), inverse exp(+2 pi i m x / N).
+template <typename T, bool INV>
+__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftPlan& pl, const C2<T>* __restrict__ tw) {
+  const int N = pl.n;
+  int Ns = 1;
+  C2<T>* src = a;
+  C2<T>* dst = b;
+  for (int p = 0; p < pl.nr; ++p) {
+    const int R = pl.r[p];
+    switch (R) {
+      case 2: stockham_pass<T, INV, 2>(src, dst, N, Ns, tw); break;
+      case 3: stockham_pass<T, INV, 3>(src, dst, N, Ns, tw); break;
+      case 4: stockham_pass<T, INV, 4>(src, dst, N, Ns, tw); break;
+      case 5: stockham_pass<T, INV, 5>(src, dst, N, Ns, tw); break;
+      case 8: stockham_pass<T, INV, 8>(src, dst, N, Ns, tw); break;
+      default: generic_pass<T, INV>(src, dst, N, Ns, R, tw); break;
+    }
+    __syncthreads();
+    C2<T>* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns *= R;
+  }
+  return src;
+}
+
+// Two complex buffers of n elements; the second one doubles as the 32-double
+// reduction scratch of k_forward (used before the transform starts).
+template <typename T>
+size_t fft_lds_bytes(int n) {
+  const size_t one = (size_t)n * sizeof(C2<T>);
+  return one + (one > 32 * sizeof(double) ? one : 32 * sizeof(double));
+}
+template size_t fft_lds_bytes<double>(int);
+template size_t fft_lds_bytes<float>(int);
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of v over the block (blockDim.x a multiple of 64, <= 1024); every
+// thread gets the result.  `red` holds 16 doubles of LDS.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+// ----------------------------------------------------------- pull helpers
+__device__ __forceinline__ int wrap_m(int x, int nx) { return x == 0 ? nx - 1 : x - 1; }
+__device__ __forceinline__ int wrap_p(int x, int nx) { return x == nx - 1 ? 0 : x + 1; }
+
+// Pre-collision charge populations at (x, j), pulled from the post-collision
+// deviations G with the electrode conditions (Table I read as: injector
+// anti-bounce-back fixing rho_c = rho0, collector zero normal gradient).
+template <typename T>
+__device__ __forceinline__ void pull_g(const Consts& c, const T* __restrict__ G, const T* __restrict__ rows,
+                                       int x, int j, T g[9]) {
+  const size_t plane = (size_t)c.ny * c.P;
+  const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+  const size_t row = (size_t)j * c.P;
+  g[0] = G[row + x];
+  g[1] = G[plane + row + xm];
+  g[3] = G[3 * plane + row + xp];
+  if (j > 0) {
+    const size_t rb = row - c.P;
+    const T ua = rows[ROW_DG_UP_AXIS * c.ny + j], ud = rows[ROW_DG_UP_DIAG * c.ny + j];
+    g[2] = G[2 * plane + rb + x] + ua;
+    g[5] = G[5 * plane + rb + xm] + ud;
+    g[6] = G[6 * plane + rb + xp] + ud;
+  } else {
+    g[2] = -G[4 * plane + row + x] + T(c.g_abb_axis);
+    g[5] = -G[7 * plane + row + x] + T(c.g_abb_diag);
+    g[6] = -G[8 * plane + row + x] + T(c.g_abb_diag);
+  }
+  if (j < c.ny - 1) {
+    const size_t ra = row + c.P;
+    const T da = rows[ROW_DG_DN_AXIS * c.ny + j], dd = rows[ROW_DG_DN_DIAG * c.ny + j];
+    g[4] = G[4 * plane + ra + x] + da;
+    g[7] = G[7 * plane + ra + xp] + dd;
+    g[8] = G[8 * plane + ra + xm] + dd;
+  } else {
+    g[4] = G[4 * plane + row + x];
+    g[7] = G[7 * plane + row + xp];
+    g[8] = G[8 * plane + row + xm];
+  }
+}
+
+// Pre-collision fluid populations at (x, j) with halfway bounce-back at both
+// electrodes (Table I) and the re-reference of rows crossed.
+template <typename T>
+__device__ __forceinline__ void pull_f(const Consts& c, const T* __restrict__ F, int x, int j, T f[9]) {
+  const size_t plane = (size_t)c.ny * c.P;
+  const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+  const size_t row = (size_t)j * c.P;
+  f[0] = F[row + x];
+  f[1] = F[plane + row + xm];
+  f[3] = F[3 * plane + row + xp];
+  if (j > 0) {
+    const size_t rb = row - c.P;
+    f[2] = F[2 * plane + rb + x] + T(c.f_up_axis);
+    f[5] = F[5 * plane + rb + xm] + T(c.f_up_diag);
+    f[6] = F[6 * plane + rb + xp] + T(c.f_up_diag);
+  } else {
+    f[2] = F[4 * plane + row + x];
+    f[5] = F[7 * plane + row + x];
+    f[6] = F[8 * plane + row + x];
+  }
+  if (j < c.ny - 1) {
+    const size_t ra = row + c.P;
+    f[4] = F[4 * plane + ra + x] + T(c.f_dn_axis);
+    f[7] = F[7 * plane + ra + xp] + T(c.f_dn_diag);
+    f[8] = F[8 * plane + ra + xm] + T(c.f_dn_diag);
+  } else {
+    f[4] = F[2 * plane + row + x];
+    f[7] = F[5 * plane + row + x];
+    f[8] = F[6 * plane + row + x];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void local_pop(const Consts& c, const T* __restrict__ A, int x, int j, T a[9]) {
+  const size_t plane = (size_t)c.ny * c.P;
+  const size_t idx = (size_t)j * c.P + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) a[i] = A[i * plane + idx];
+}
+
+// ------------------------------------------- forward transform (with gather)
+// One block per pair of rows (j0 = 2 b, j1 = 2 b + 1) packed as the real and
+// imaginary parts of one complex transform.  Writes the source spectrum
+// s_m = -DFT(rho_c - r)_m / eps for m = 1 .. nx/2 (Eq. 4, 19) and the FP64
+// row sums of the charge deviation (the m = 0 mode).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
+                                                 const double* __restrict__ drc_field, FftPlan pl,
+                                                 const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
+                                                 double* __restrict__ dcsum) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T>* a = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* b = a + pl.n;
+  double* red = reinterpret_cast<double*>(b);  // idle until the transform
+  const int j0 = 2 * blockIdx.x, j1 = j0 + 1;
+  const bool has1 = j1 < c.ny;
+  double s0 = 0.0, s1 = 0.0;
+  for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
+    T v[2] = {T(0), T(0)};
+    for (int q = 0; q < (has1 ? 2 : 1); ++q) {
+      const int j = j0 + q;
+      if (MODE == 2) {
+        v[q] = T(drc_field[(size_t)j * c.nx + x]);
+      } else {
+        T g[9];
+        if (MODE == 0)
+          pull_g<T>(c, G, rows, x, j, g);
+        else
+          local_pop<T>(c, G, x, j, g);
+        v[q] = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+      }
+    }
+    a[x] = C2<T>{v[0], v[1]};
+    s0 += (double)v[0];
+    s1 += (double)v[1];
+  }
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red + 16);
+  if (threadIdx.x == 0) {
+    dcsum[j0] = s0;
+    if (has1) dcsum[j1] = s1;
+  }
+  __syncthreads();
+  C2<T>* z = fft_lds<T, false>(a, b, pl, tw);
+  const T sc = T(-0.5 / c.eps);
+  const int N = pl.n;
+  for (int m = threadIdx.x; m < c.M; m += blockDim.x) {
+    C2<T> X = {T(0), T(0)}, Y = {T(0), T(0)};
+    if (m > 0) {
+      const C2<T> zm = z[m], zn = z[N - m];
+      // X = (Z_m + conj Z_{N-m}) / 2,  Y = (Z_m - conj Z_{N-m}) / (2 i)
+      X = C2<T>{(zm.re + zn.re) * sc, (zm.im - zn.im) * sc};
+      Y = C2<T>{(zm.im + zn.im) * sc, (zn.re - zm.re) * sc};
+    }
+    spec[(size_t)j0 * c.MP + m] = X;
+    if (has1) spec[(size_t)j1 * c.MP + m] = Y;
+  }
+}
+
+// --------------------------------------------------- x-mean mode (m = 0)
+// The x-mean potential by integrating Gauss's law twice (flux form of the
+// m = 0 row of Eq. 18 / 24 with the electrode ghost rows):
+//   sbar(j) = -(r(j) + dcsum(j) / nx) / eps
+//   D(j) = D(-1) + S(j),  S = running sum of sbar,
+//   D(-1) = (phi_upper - phi_lower)/ny - (S(ny-1) + 2 sum_{k<ny-1} S(k)) / (2 ny)
+//   phi_mean(j) = phi_lower + D(-1)/2 + sum_{k<j} D(k),  E_y mean = -(D(j) + D(j-1))/2
+// One block; FP64 throughout.
+__global__ void __launch_bounds__(1024) k_mean_mode(Consts c, double* __restrict__ rowsd,
+                                                     double* __restrict__ dmean) {
+  __shared__ double part[1024];
+  __shared__ double red[32];
+  const int ny = c.ny;
+  const int nt = blockDim.x;
+  const int chunk = (ny + nt - 1) / nt;
+  const int lo = threadIdx.x * chunk;
+  const int hi = min(lo + chunk, ny);
+  const double* r = rowsd + ROWD_R * ny;
+  const double* dcs = rowsd + ROWD_DCSUM * ny;
+  // local inclusive sums of sbar, stored in dmean[1 + j]
+  double acc = 0.0;
+  for (int j = lo; j < hi; ++j) {
+    const double sb = -(r[j] + dcs[j] / (double)c.nx) / c.eps;
+    acc += sb;
+    dmean[1 + j] = acc;
+  }
+  // exclusive scan of the chunk totals (Hillis-Steele over the block)
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    const double v = threadIdx.x >= o ? part[threadIdx.x - o] : 0.0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const double off = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
+  double tsum = 0.0;  // sum of S(k) for k < ny - 1 over this chunk
+  for (int j = lo; j < hi; ++j) {
+    const double S = dmean[1 + j] + off;
+    dmean[1 + j] = S;
+    if (j < ny - 1) tsum += S;
+  }
+  const double Ttot = block_sum(tsum, red);
+  __syncthreads();
+  const double Slast = dmean[ny];
+  const double dlow = (0.0 - 1.0) / (double)ny - (Slast + 2.0 * Ttot) / (2.0 * ny);
+  __syncthreads();
+  // D(j) = D(-1) + S(j); potential = exclusive running sum of D
+  double pacc = 0.0;
+  for (int j = lo; j < hi; ++j) {
+    const double D = dlow + dmean[1 + j];
+    dmean[1 + j] = D;
+    pacc += D;
+  }
+  __syncthreads();
+  part[threadIdx.x] = pacc;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    const double v = threadIdx.x >= o ? part[threadIdx.x - o] : 0.0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  double run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
+  const double phi0 = 1.0 + 0.5 * dlow;
+  double* eym = rowsd + ROWD_EYM * ny;
+  double* phim = rowsd + ROWD_PHIM * ny;
+  if (threadIdx.x == 0) dmean[0] = dlow;
+  for (int j = lo; j < hi; ++j) {
+    const double Dj = dmean[1 + j];
+    const double Djm = j > 0 ? dmean[j] : dlow;
+    phim[j] = phi0 + run;
+    eym[j] = -(Dj + Djm) / 2.0;
+    run += Dj;
+  }
+}
+
+// ------------------------------------------------- per-wavenumber solves
+// m = 1 .. nx/2: phi(j+1) - (2 + kappa_m^2) phi(j) + phi(j-1) = s(j) with
+// homogeneous ghost closures (Eq. 20, 24-25 as a tridiagonal per m), by
+// elimination with the precomputed factors cp = 1 / (b_j - cp_{j-1}).
+template <typename T>
+__global__ void __launch_bounds__(64) k_tridiag(Consts c, const T* __restrict__ cp, C2<T>* __restrict__ spec) {
+  const int m = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= c.M) return;
+  const size_t MP = c.MP;
+  C2<T> dprev = {T(0), T(0)};
+  for (int j = 0; j < c.ny; ++j) {
+    const T f = cp[j * MP + m];
+    const C2<T> s = spec[j * MP + m];
+    const C2<T> d = {(s.re - dprev.re) * f, (s.im - dprev.im) * f};
+    spec[j * MP + m] = d;
+    dprev = d;
+  }
+  C2<T> xn = dprev;
+  for (int j = c.ny - 2; j >= 0; --j) {
+    const T f = cp[j * MP + m];
+    const C2<T> d = spec[j * MP + m];
+    const C2<T> xv = {d.re - f * xn.re, d.im - f * xn.im};
+    spec[j * MP + m] = xv;
+    xn = xv;
+  }
+}
+
+// --------------------------------------------------- inverse transform
+// Pair of rows per block: Z_m = X_m + i Y_m with the Hermitian halves of the
+// two solved spectra (m = 0 left out: it lives in the x-mean row), inverse
+// transform, 1/nx, real / imaginary parts to the two rows of phi.
+template <typename T>
+__global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restrict__ spec, FftPlan pl,
+                                                 const C2<T>* __restrict__ tw, T* __restrict__ phi) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T>* a = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* b = a + pl.n;
+  const int j0 = 2 * blockIdx.x, j1 = j0 + 1;
+  const bool has1 = j1 < c.ny;
+  const int N = pl.n;
+  for (int m = threadIdx.x; m < N; m += blockDim.x) {
+    C2<T> Z = {T(0), T(0)};
+    if (m > 0) {
+      const bool lowh = m < c.M;
+      const int mm = lowh ? m : N - m;
+      C2<T> X = spec[(size_t)j0 * c.MP + mm];
+      C2<T> Y = has1 ? spec[(size_t)j1 * c.MP + mm] : C2<T>{T(0), T(0)};
+      if (!lowh) {
+        X.im = -X.im;
+        Y.im = -Y.im;
+      }
+      Z = C2<T>{X.re - Y.im, X.im + Y.re};
+    }
+    a[m] = Z;
+  }
+  __syncthreads();
+  C2<T>* z = fft_lds<T, true>(a, b, pl, tw);
+  const T inv = T(1.0 / (double)N);
+  for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
+    phi[(size_t)j0 * c.P + x] = z[x].re * inv;
+    if (has1) phi[(size_t)j1 * c.P + x] = z[x].im * inv;
+  }
+}
+
+// ------------------------------------------- fused collide (and stream)
+// One thread per node.  PULL: gathers the pre-collision populations from the
+// post-collision arrays with the wall rules (the streaming of Eq. 8-9);
+// otherwise reads them at the node (first collision of the initial state).
+// Then the moments (Eq. 5-7), E = -grad phi (central differences, the mean
+// row in FP64), the equilibria (Eq. 10-11), the source (Eq. 12) and the TRT
+// collisions (Eq. 8-9, 13-15); writes the post-collision deviations.
+template <typename T, bool PULL, bool EMIT>
+__global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__ Fin, const T* __restrict__ Gin,
+                                                 T* __restrict__ Fout, T* __restrict__ Gout,
+                                                 const T* __restrict__ phi, const T* __restrict__ rows,
+                                                 const double* __restrict__ rowsd, double* __restrict__ mom) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= c.nx || j >= c.ny) return;
+  T f[9], g[9];
+  if (PULL) {
+    pull_f<T>(c, Fin, x, j, f);
+    pull_g<T>(c, Gin, rows, x, j, g);
+  } else {
+    local_pop<T>(c, Fin, x, j, f);
+    local_pop<T>(c, Gin, x, j, g);
+  }
+  // moments
+  const T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const T rho = rows[ROW_RHO_REF * c.ny + j] + drho;
+  const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  const T drc = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+  const T rc = rows[ROW_R * c.ny + j] + drc;
+  // electric field
+  const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+  const size_t row = (size_t)j * c.P;
+  const T pc = phi[row + x];
+  const T pxp = phi[row + xp], pxm = phi[row + xm];
+  const T pyp = j < c.ny - 1 ? phi[row + c.P + x] : -pc;
+  const T pym = j > 0 ? phi[row - c.P + x] : -pc;
+  const T ex = -(pxp - pxm) / T(2);
+  const T ey = T(rowsd[ROWD_EYM * c.ny + j]) - (pyp - pym) / T(2);
+  const T fx = rc * ex + T(c.bx);
+  const T fy = rc * ey;
+  const T ux = (jx + T(0.5) * fx) / rho;
+  const T uy = (jy + T(0.5) * fy) / rho;
+  const T vx = ux + T(c.K) * ex;
+  const T vy = uy + T(c.K) * ey;
+  if (EMIT) {
+    const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
+    mom[k] = (double)drho;
+    mom[n + k] = (double)ux;
+    mom[2 * n + k] = (double)uy;
+    mom[3 * n + k] = (double)drc;
+  }
+  const T w0 = T(4.0 / 9.0), wa = T(1.0 / 9.0), wd = T(1.0 / 36.0);
+  const T uu = ux * ux + uy * uy;
+  const T vv = vx * vx + vy * vy;
+  // f^eq_i - w_i rho_ref = w_i drho + w_i rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+  // F_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F
+  // charge: g^eq_i - R_i = w_i drc + w_i rc (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)
+  const T wp = T(c.wp), wm = T(c.wm), wgp = T(c.wgp), wgm = T(c.wgm);
+  const T sp = T(1) - T(0.5) * wp, sm = T(1) - T(0.5) * wm;
+  const T uF = ux * fx + uy * fy;
+  T fo[9], go[9];
+  {  // rest direction
+    const T feq0 = w0 * drho + w0 * rho * (-T(1.5) * uu);
+    const T F0 = w0 * (-T(3) * uF);
+    fo[0] = f[0] - wp * (f[0] - feq0) + sp * F0;
+    const T geq0 = w0 * drc + w0 * rc * (-T(1.5) * vv);
+    go[0] = g[0] - wgp * (g[0] - geq0);
+  }
+  // pairs (i, opp): (1,3), (2,4), (5,7), (6,8)
+  const int pi[4] = {1, 2, 5, 6}, po[4] = {3, 4, 7, 8};
+  const T cxs[4] = {T(1), T(0), T(1), T(-1)}, cys[4] = {T(0), T(1), T(1), T(1)};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = pi[q], o = po[q];
+    const T w = q < 2 ? wa : wd;
+    const T cx = cxs[q], cy = cys[q];
+    const T cu = cx * ux + cy * uy;
+    const T cv = cx * vx + cy * vy;
+    const T cF = cx * fx + cy * fy;
+    // equilibria at i (c) and at opp (-c)
+    const T fe_i = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+    const T fe_o = w * drho + w * rho * (-T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+    const T Fs_i = w * (T(3) * (cF - uF) + T(9) * cu * cF);
+    const T Fs_o = w * (T(3) * (-cF - uF) + T(9) * cu * cF);
+    const T ge_i = w * drc + w * rc * (T(3) * cv + T(4.5) * cv * cv - T(1.5) * vv);
+    const T ge_o = w * drc + w * rc * (-T(3) * cv + T(4.5) * cv * cv - T(1.5) * vv);
+    const T fp = T(0.5) * (f[i] + f[o]), fm = T(0.5) * (f[i] - f[o]);
+    const T ep = T(0.5) * (fe_i + fe_o), em = T(0.5) * (fe_i - fe_o);
+    const T Sp = T(0.5) * (Fs_i + Fs_o), Sm = T(0.5) * (Fs_i - Fs_o);
+    const T relp = wp * (fp - ep), relm = wm * (fm - em);
+    fo[i] = f[i] - relp - relm + sp * Sp + sm * Sm;
+    fo[o] = f[o] - relp + relm + sp * Sp - sm * Sm;
+    const T gp = T(0.5) * (g[i] + g[o]), gm = T(0.5) * (g[i] - g[o]);
+    const T hp = T(0.5) * (ge_i + ge_o), hm = T(0.5) * (ge_i - ge_o);
+    const T grp = wgp * (gp - hp), grm = wgm * (gm - hm);
+    go[i] = g[i] - grp - grm;
+    go[o] = g[o] - grp + grm;
+  }
+  const size_t plane = (size_t)c.ny * c.P;
+  const size_t idx = row + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    Fout[i * plane + idx] = fo[i];
+    Gout[i * plane + idx] = go[i];
+  }
+}
+
+// ------------------------------------------------------------ init kernels
+__device__ __forceinline__ double splitmix_uniform_pm1(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  const double u = (double)(z >> 11) * 0x1.0p-53;
+  return 2.0 * u - 1.0;
+}
+
+// Initial charge deviation rho_c^0 - r into mom plane 3 (FP64).
+template <typename T>
+__global__ void __launch_bounds__(256) k_init_charge(Consts c, const double* __restrict__ rowsd, double* __restrict__ mom) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= c.nx) return;
+  const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
+  const double rcl = rowsd[ROWD_RC_CLOSED * c.ny + j];
+  double rc0 = rcl;
+  if (c.init_mode == 0) {
+    const double xi = splitmix_uniform_pm1(c.seed, k);
+    rc0 = rcl * (1.0 + c.noise_amp * xi);
+  }
+  mom[3 * n + k] = rc0 - rowsd[ROWD_R * c.ny + j];
+}
+
+// Pre-collision equilibria of the initial state at the nodes of buffer dst:
+// f^0 = f^eq(rho_ref, u^0), g^0 = g^eq(rho_c^0, u^0 + K E^0), E^0 from the
+// potential just solved for rho_c^0.  u^0 = 0, or the Eq. 29 perturbation.
+template <typename T>
+__global__ void __launch_bounds__(256) k_init_populations(Consts c, T* __restrict__ F, T* __restrict__ G,
+                                                          const T* __restrict__ phi, const double* __restrict__ rowsd,
+                                                          const double* __restrict__ mom) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= c.nx) return;
+  const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
+  const double drc = mom[3 * n + k];
+  const double rc = rowsd[ROWD_R * c.ny + j] + drc;
+  const double rho = rowsd[ROWD_RHO_REF * c.ny + j];
+  double ux = 0.0, uy = 0.0;
+  if (c.init_mode == 1) {
+    const double twopi = 6.283185307179586;
+    const double Lx = (double)c.nx / (double)c.ny, Ly = 1.0;
+    const double xx = (double)x / (double)c.ny, yy = ((double)j + 0.5) / (double)c.ny;
+    ux = 1e-3 * c.u0 * Lx * sin(twopi * yy / Ly) * sin(twopi * xx / Lx);
+    uy = 1e-3 * c.u0 * Ly * (cos(twopi * yy / Ly) - 1.0) * cos(twopi * xx / Lx);
+  }
+  const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+  const size_t row = (size_t)j * c.P;
+  const double pc = (double)phi[row + x];
+  const double pyp = j < c.ny - 1 ? (double)phi[row + c.P + x] : -pc;
+  const double pym = j > 0 ? (double)phi[row - c.P + x] : -pc;
+  const double ex = -((double)phi[row + xp] - (double)phi[row + xm]) / 2.0;
+  const double ey = rowsd[ROWD_EYM * c.ny + j] - (pyp - pym) / 2.0;
+  const double vx = ux + c.K * ex, vy = uy + c.K * ey;
+  const double cxv[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const double cyv[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const double wv[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                        1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  const double uu = ux * ux + uy * uy, vv = vx * vx + vy * vy;
+  const size_t plane = (size_t)c.ny * c.P;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double cu = cxv[i] * ux + cyv[i] * uy;
+    const double cv = cxv[i] * vx + cyv[i] * vy;
+    const double fe = wv[i] * 0.0 + wv[i] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    const double ge = wv[i] * drc + wv[i] * rc * (3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+    F[i * plane + row + x] = (T)fe;
+    G[i * plane + row + x] = (T)ge;
+  }
+}
+
+// Nondimensional FP64 output fields of the current state.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fields(Consts c, const double* __restrict__ mom, const T* __restrict__ phi,
+                                                const double* __restrict__ rowsd, double* rho, double* ux,
+                                                double* uy, double* rho_c, double* phio) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= c.nx) return;
+  const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
+  if (rho) rho[k] = rowsd[ROWD_RHO_REF * c.ny + j] + mom[k];
+  if (ux) ux[k] = mom[n + k] / c.u0;
+  if (uy) uy[k] = mom[2 * n + k] / c.u0;
+  if (rho_c) rho_c[k] = (rowsd[ROWD_R * c.ny + j] + mom[3 * n + k]) * c.H * c.H / c.eps;
+  if (phio) phio[k] = rowsd[ROWD_PHIM * c.ny + j] + (double)phi[(size_t)j * c.P + x];
+}
+
+// Charge deviation field from a nondimensional charge density (Poisson entry).
+__global__ void __launch_bounds__(256) k_charge_in(Consts c, const double* __restrict__ rc_nd,
+                                                   const double* __restrict__ rowsd, double* __restrict__ mom) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= c.nx) return;
+  const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
+  mom[3 * n + k] = rc_nd[k] * c.eps / (c.H * c.H) - rowsd[ROWD_R * c.ny + j];
+}
+
+// Global FP64 diagnostics of the emitted moments (one block, fixed order).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_stats(Consts c, const double* __restrict__ mom, const T* __restrict__ phi,
+                                                const double* __restrict__ rowsd, double* __restrict__ out) {
+  __shared__ double red[32];
+  const size_t n = (size_t)c.ny * c.nx;
+  double s_drho = 0, s_rc = 0, s_uy2 = 0, mx_u = 0, mn_rc = 1e300, bad = 0, mx_ex = 0;
+  for (size_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const int j = (int)(k / c.nx), x = (int)(k % c.nx);
+    const double drho = mom[k], ux = mom[n + k], uy = mom[2 * n + k];
+    const double rc = rowsd[ROWD_R * c.ny + j] + mom[3 * n + k];
+    const double rho = rowsd[ROWD_RHO_REF * c.ny + j] + drho;
+    s_drho += (rho - 1.0);
+    s_rc += rc;
+    s_uy2 += uy * uy;
+    mx_u = fmax(mx_u, sqrt(ux * ux + uy * uy));
+    mn_rc = fmin(mn_rc, rc);
+    if (!(rho > 0.0) || !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(rc)) bad += 1.0;
+    const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+    const double ex = -((double)phi[(size_t)j * c.P + xp] - (double)phi[(size_t)j * c.P + xm]) / 2.0;
+    mx_ex = fmax(mx_ex, fabs(ex));
+  }
+  s_drho = block_sum(s_drho, red);
+  __syncthreads();
+  s_rc = block_sum(s_rc, red);
+  __syncthreads();
+  s_uy2 = block_sum(s_uy2, red);
+  __syncthreads();
+  bad = block_sum(bad, red);
+  __syncthreads();
+  // max / min through the same LDS
+  __shared__ double mx[1024], mn[1024], me[1024];
+  mx[threadIdx.x] = mx_u;
+  mn[threadIdx.x] = mn_rc;
+  me[threadIdx.x] = mx_ex;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
+      mn[threadIdx.x] = fmin(mn[threadIdx.x], mn[threadIdx.x + o]);
+      me[threadIdx.x] = fmax(me[threadIdx.x], me[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[1] = s_drho;
+    out[2] = s_rc;
+    out[3] = sqrt(s_uy2 / (double)n);
+    out[4] = mx[0];
+    out[5] = mn[0];
+    out[6] = bad;
+    out[7] = me[0];
+  }
+}
+
+// ------------------------------------------------------------- launchers
+static inline dim3 node_grid2(const Consts& c, dim3 blk) {
+  return dim3((c.nx + blk.x - 1) / blk.x, (c.ny + blk.y - 1) / blk.y);
+}
+
+template <typename T>
+hipError_t launch_init_charge(const Consts& c, const Bufs& b, hipStream_t s) {
+  dim3 blk(256), grd((c.nx + 255) / 256, c.ny);
+  hipLaunchKernelGGL(k_init_charge<T>, grd, blk, 0, s, c, b.rowsd, b.mom);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_populations(const Consts& c, const Bufs& b, int dst, hipStream_t s) {
+  dim3 blk(256), grd((c.nx + 255) / 256, c.ny);
+  hipLaunchKernelGGL(k_init_populations<T>, grd, blk, 0, s, c, (T*)b.f[dst], (T*)b.g[dst], (const T*)b.phi,
+                     b.rowsd, b.mom);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src, hipStream_t s) {
+  dim3 blk(256), grd((c.ny + 1) / 2);
+  const size_t lds = fft_lds_bytes<T>(pl.n);
+  const T* G = (const T*)b.g[src];
+  const T* rows = (const T*)b.rows;
+  const double* fld = b.mom + 3 * (size_t)c.ny * c.nx;
+  C2<T>* spec = (C2<T>*)b.spec;
+  const C2<T>* tw = (const C2<T>*)b.tw;
+  double* dcs = b.rowsd + ROWD_DCSUM * c.ny;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_forward<T, 0>), grd, blk, lds, s, c, G, rows, fld, pl, tw, spec, dcs);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_forward<T, 1>), grd, blk, lds, s, c, G, rows, fld, pl, tw, spec, dcs);
+  else
+    hipLaunchKernelGGL((k_forward<T, 2>), grd, blk, lds, s, c, G, rows, fld, pl, tw, spec, dcs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mean_mode(const Consts& c, const Bufs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_mean_mode, dim3(1), dim3(1024), 0, s, c, b.rowsd, b.dmean);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
+  const int nm = c.M - 1;
+  if (nm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tridiag<T>, dim3((nm + 63) / 64), dim3(64), 0, s, c, (const T*)b.cp, (C2<T>*)b.spec);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, hipStream_t s) {
+  dim3 blk(256), grd((c.ny + 1) / 2);
+  const size_t lds = fft_lds_bytes<T>(pl.n);
+  hipLaunchKernelGGL(k_inverse<T>, grd, blk, lds, s, c, (const C2<T>*)b.spec, pl, (const C2<T>*)b.tw, (T*)b.phi);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst, hipStream_t s) {
+  dim3 blk(64, 4);
+  dim3 grd = node_grid2(c, blk);
+  const T* Fin = (const T*)b.f[src];
+  const T* Gin = (const T*)b.g[src];
+  T* Fout = (T*)b.f[dst];
+  T* Gout = (T*)b.g[dst];
+  const T* phi = (const T*)b.phi;
+  const T* rows = (const T*)b.rows;
+  if (pull && emit)
+    hipLaunchKernelGGL((k_collide<T, true, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+  else if (pull)
+    hipLaunchKernelGGL((k_collide<T, true, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+  else if (emit)
+    hipLaunchKernelGGL((k_collide<T, false, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+  else
+    hipLaunchKernelGGL((k_collide<T, false, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fields(const Consts& c, const Bufs& b, double* rho, double* ux, double* uy, double* rho_c,
+                         double* phi, hipStream_t s) {
+  dim3 blk(256), grd((c.nx + 255) / 256, c.ny);
+  hipLaunchKernelGGL(k_fields<T>, grd, blk, 0, s, c, b.mom, (const T*)b.phi, b.rowsd, rho, ux, uy, rho_c, phi);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_nd, hipStream_t s) {
+  dim3 blk(256), grd((c.nx + 255) / 256, c.ny);
+  hipLaunchKernelGGL(k_charge_in, grd, blk, 0, s, c, rho_c_nd, b.rowsd, b.mom);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats<T>, dim3(1), dim3(1024), 0, s, c, b.mom, (const T*)b.phi, b.rowsd, b.stats);
+  return hipGetLastError();
+}
+
+#define EC_INSTANTIATE(T)                                                                                   \
+  template hipError_t launch_init_charge<T>(const Consts&, const Bufs&, hipStream_t);                       \
+  template hipError_t launch_init_populations<T>(const Consts&, const Bufs&, int, hipStream_t);             \
+  template hipError_t launch_forward<T>(const Consts&, const Bufs&, const FftPlan&, int, int, hipStream_t); \
+  template hipError_t launch_mean_mode<T>(const Consts&, const Bufs&, hipStream_t);                         \
+  template hipError_t launch_tridiag<T>(const Consts&, const Bufs&, hipStream_t);                           \
+  template hipError_t launch_inverse<T>(const Consts&, const Bufs&, const FftPlan&, hipStream_t);           \
+  template hipError_t launch_collide<T>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);     \
+  template hipError_t launch_fields<T>(const Consts&, const Bufs&, double*, double*, double*, double*,       \
+                                       double*, hipStream_t);                                               \
+  template hipError_t launch_charge_in<T>(const Consts&, const Bufs&, const double*, hipStream_t);          \
+  template hipError_t launch_stats<T>(const Consts&, const Bufs&, hipStream_t);
+
+EC_INSTANTIATE(double)
+EC_INSTANTIATE(float)
+
+}  // namespace ec

@@ -1,0 +1,187 @@
+"""Python binding of the C ABI in include/lbm_ec.h (ctypes).
+
+Argument marshalling only: every step of the time loop runs in the HIP
+library.  PyTorch supplies the device workspace and the stream.  If the
+native library is missing, every call raises; there is no fallback.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_ec.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, EBUSY = 0, 1, 2, 3, 4, 5
+FP64, FP32_DEV = 0, 1
+INIT_NOISE, INIT_EQ29, INIT_REST = 0, 1, 2
+RATES_ANTISYMMETRIC, RATES_SYMMETRIC = 0, 1
+
+_PRECISION = {"fp64": FP64, "fp32": FP32_DEV, "fp32_dev": FP32_DEV}
+_INIT = {"noise": INIT_NOISE, "eq29": INIT_EQ29, "rest": INIT_REST}
+_RATES = {"antisymmetric": RATES_ANTISYMMETRIC, "symmetric": RATES_SYMMETRIC}
+
+
+class LbmEcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbm_ec error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("T", ctypes.c_double),
+        ("C", ctypes.c_double),
+        ("M", ctypes.c_double),
+        ("Fe", ctypes.c_double),
+        ("tau_plus", ctypes.c_double),
+        ("Lambda", ctypes.c_double),
+        ("Lambda_g", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("init_mode", ctypes.c_int32),
+        ("noise_amp", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("instance_id", ctypes.c_int32),
+        ("charge_rates", ctypes.c_int32),
+        ("body_force_x", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded native library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"native library {LIB_PATH} is missing; build it with "
+                           "python -m paper_1812_05711_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(Params)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.lbm_ec_params_default.argtypes = [P]
+    L.lbm_ec_params_default.restype = ctypes.c_int
+    L.lbm_ec_validate.argtypes = [P]
+    L.lbm_ec_validate.restype = ctypes.c_int
+    L.lbm_ec_workspace_bytes.argtypes = [P]
+    L.lbm_ec_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_ec_create.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.lbm_ec_create.restype = ctypes.c_int
+    L.lbm_ec_step.argtypes = [vp, ctypes.c_int64]
+    L.lbm_ec_step.restype = ctypes.c_int
+    L.lbm_ec_steps_done.argtypes = [vp]
+    L.lbm_ec_steps_done.restype = ctypes.c_int64
+    L.lbm_ec_fields.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.lbm_ec_fields.restype = ctypes.c_int
+    L.lbm_ec_poisson.argtypes = [vp, vp, vp]
+    L.lbm_ec_poisson.restype = ctypes.c_int
+    L.lbm_ec_stats.argtypes = [vp, dp]
+    L.lbm_ec_stats.restype = ctypes.c_int
+    L.lbm_ec_destroy.argtypes = [vp]
+    L.lbm_ec_destroy.restype = None
+    L.lbm_ec_last_error.argtypes = []
+    L.lbm_ec_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != OK:
+        raise LbmEcError(code, lib().lbm_ec_last_error().decode())
+
+
+def make_params(nx, ny, T=200.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25,
+                Lambda_g=1e-6, precision="fp64", init_mode="noise", noise_amp=1e-3,
+                seed=181205711, instance_id=0, charge_rates="antisymmetric", body_force_x=0.0):
+    p = Params()
+    _check(lib().lbm_ec_params_default(ctypes.byref(p)))
+    p.nx, p.ny = int(nx), int(ny)
+    p.T, p.C, p.M, p.Fe = float(T), float(C), float(M), float(Fe)
+    p.tau_plus, p.Lambda, p.Lambda_g = float(tau_plus), float(Lambda), float(Lambda_g)
+    p.precision = _PRECISION[precision] if isinstance(precision, str) else int(precision)
+    p.init_mode = _INIT[init_mode] if isinstance(init_mode, str) else int(init_mode)
+    p.noise_amp = float(noise_amp)
+    p.seed = int(seed) % (1 << 64)
+    p.instance_id = int(instance_id)
+    p.charge_rates = _RATES[charge_rates] if isinstance(charge_rates, str) else int(charge_rates)
+    p.body_force_x = float(body_force_x)
+    return p
+
+
+def workspace_bytes(p: Params) -> int:
+    n = lib().lbm_ec_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        _check(lib().lbm_ec_validate(ctypes.byref(p)))
+    return n
+
+
+class Simulation:
+    """One simulation on a GPU: its workspace is a torch uint8 tensor."""
+
+    def __init__(self, device="cuda:0", stream=None, **kw):
+        self.device = torch.device(device)
+        self.params = make_params(**kw)
+        nbytes = workspace_bytes(self.params)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            _check(lib().lbm_ec_create(ctypes.byref(self.params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                       nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def nx(self):
+        return self.params.nx
+
+    @property
+    def ny(self):
+        return self.params.ny
+
+    def step(self, n=1):
+        _check(lib().lbm_ec_step(self._h, int(n)))
+        return self
+
+    def steps_done(self):
+        return int(lib().lbm_ec_steps_done(self._h))
+
+    def fields(self):
+        """Dict of nondimensional FP64 device tensors (ny, nx): rho, ux, uy, rho_c, phi."""
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+               for k in ("rho", "ux", "uy", "rho_c", "phi")}
+        _check(lib().lbm_ec_fields(self._h, *[ctypes.c_void_p(out[k].data_ptr())
+                                              for k in ("rho", "ux", "uy", "rho_c", "phi")]))
+        return out
+
+    def poisson(self, rho_c: torch.Tensor) -> torch.Tensor:
+        """phi for a nondimensional charge density (testing entry point)."""
+        rho_c = rho_c.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(rho_c.shape) == (self.ny, self.nx)
+        phi = torch.empty_like(rho_c)
+        _check(lib().lbm_ec_poisson(self._h, ctypes.c_void_p(rho_c.data_ptr()), ctypes.c_void_p(phi.data_ptr())))
+        return phi
+
+    def stats(self):
+        buf = (ctypes.c_double * 8)()
+        code = lib().lbm_ec_stats(self._h, buf)
+        if code not in (OK, EUNSTABLE):
+            _check(code)
+        names = ["steps", "mass_dev", "charge", "rms_uy", "max_u", "min_rho_c", "bad", "max_ex"]
+        return dict(zip(names, list(buf))), code == OK
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_ec_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
