@@ -158,6 +158,17 @@ int lbm_ec_poisson(lbm_ec_t* h, const double* d_rho_c, double* d_phi);
  * Returns EUNSTABLE (after filling out) if out[6] > 0. */
 int lbm_ec_stats(lbm_ec_t* h, double* out);
 
+/* Kernel timing for measurement.  lbm_ec_profile_begin starts recording a
+ * HIP event pair around every kernel the handle enqueues on its stream;
+ * lbm_ec_profile_end stops, waits for the last event and returns, per kernel
+ * class, the summed elapsed milliseconds and the launch count in ms[k] and
+ * launches[k] for k < n.  Classes: 0 forward transform (with the charge
+ * gather), 1 x-mean mode, 2 per-wavenumber solves, 3 inverse transform,
+ * 4 collide-stream.  The events are created on first use and kept by the
+ * handle (host-side driver objects, no device memory). */
+int lbm_ec_profile_begin(lbm_ec_t* h);
+int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
+
 /* Releases the handle (host memory only; the caller frees the workspace). */
 void lbm_ec_destroy(lbm_ec_t* h);
 

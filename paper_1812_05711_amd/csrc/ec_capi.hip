@@ -141,8 +141,19 @@ int validate(const lbm_ec_params* p) {
 
 }  // namespace
 
+// Kernel classes timed by the profiling hooks.
+enum { KC_FORWARD = 0, KC_MEAN, KC_TRIDIAG, KC_INVERSE, KC_COLLIDE, KC_COUNT };
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pool, reused across profiling windows
+  std::vector<int> cls;        // class of each recorded pair
+  size_t used = 0;             // events used in the current window
+};
+
 struct lbm_ec {
   lbm_ec_params p;
+  Profiler prof;
   Layout L;
   ec::Consts c;
   ec::Bufs b;
@@ -285,12 +296,36 @@ int setup(lbm_ec* h, unsigned char* ws) {
   return LBM_EC_OK;
 }
 
+// Records an event on the handle's stream when profiling (start of a pair
+// when `cls` >= 0, end of the open pair when `cls` < 0).
+int prof_mark(lbm_ec* h, int cls) {
+  Profiler& P = h->prof;
+  if (!P.on) return LBM_EC_OK;
+  if (P.used == P.ev.size()) {
+    hipEvent_t e;
+    EC_HIP(hipEventCreate(&e));
+    P.ev.push_back(e);
+  }
+  if (cls >= 0) P.cls.push_back(cls);
+  EC_HIP(hipEventRecord(P.ev[P.used++], h->s));
+  return LBM_EC_OK;
+}
+
+#define EC_TIMED(h, cls, launch)           \
+  do {                                     \
+    int rc_ = prof_mark((h), (cls));       \
+    if (rc_) return rc_;                   \
+    EC_HIP(launch);                        \
+    rc_ = prof_mark((h), -1);              \
+    if (rc_) return rc_;                   \
+  } while (0)
+
 template <typename T>
 int poisson_chain(lbm_ec* h, int mode, int src) {
-  EC_HIP(ec::launch_forward<T>(h->c, h->b, h->plan, mode, src, h->s));
-  EC_HIP(ec::launch_mean_mode<T>(h->c, h->b, h->s));
-  EC_HIP(ec::launch_tridiag<T>(h->c, h->b, h->s));
-  EC_HIP(ec::launch_inverse<T>(h->c, h->b, h->plan, h->s));
+  EC_TIMED(h, KC_FORWARD, (ec::launch_forward<T>(h->c, h->b, h->plan, mode, src, h->s)));
+  EC_TIMED(h, KC_MEAN, (ec::launch_mean_mode<T>(h->c, h->b, h->s)));
+  EC_TIMED(h, KC_TRIDIAG, (ec::launch_tridiag<T>(h->c, h->b, h->s)));
+  EC_TIMED(h, KC_INVERSE, (ec::launch_inverse<T>(h->c, h->b, h->plan, h->s)));
   return LBM_EC_OK;
 }
 
@@ -316,7 +351,7 @@ int run_steps(lbm_ec* h, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const int src = h->cur, dst = 1 - h->cur;
     if ((rc = poisson_chain<T>(h, 0, src))) return rc;
-    EC_HIP(ec::launch_collide<T>(h->c, h->b, true, k == n - 1, src, dst, h->s));
+    EC_TIMED(h, KC_COLLIDE, (ec::launch_collide<T>(h->c, h->b, true, k == n - 1, src, dst, h->s)));
     h->cur = dst;
     h->steps += 1;
   }
@@ -443,7 +478,42 @@ int lbm_ec_stats(lbm_ec_t* h, double* out) {
   return LBM_EC_OK;
 }
 
-void lbm_ec_destroy(lbm_ec_t* h) { delete h; }
+int lbm_ec_profile_begin(lbm_ec_t* h) {
+  if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
+  h->prof.on = true;
+  h->prof.used = 0;
+  h->prof.cls.clear();
+  return LBM_EC_OK;
+}
+
+int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n) {
+  if (!h || !ms || !launches) return fail(LBM_EC_EINVAL, "NULL argument");
+  Profiler& P = h->prof;
+  P.on = false;
+  for (int k = 0; k < n; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  if (P.used) EC_HIP(hipEventSynchronize(P.ev[P.used - 1]));
+  for (size_t q = 0; q < P.cls.size(); ++q) {
+    float t = 0.f;
+    EC_HIP(hipEventElapsedTime(&t, P.ev[2 * q], P.ev[2 * q + 1]));
+    const int c = P.cls[q];
+    if (c < n) {
+      ms[c] += (double)t;
+      launches[c] += 1;
+    }
+  }
+  P.used = 0;
+  P.cls.clear();
+  return LBM_EC_OK;
+}
+
+void lbm_ec_destroy(lbm_ec_t* h) {
+  if (!h) return;
+  for (hipEvent_t e : h->prof.ev) (void)hipEventDestroy(e);
+  delete h;
+}
 
 const char* lbm_ec_last_error(void) { return g_err.c_str(); }
 

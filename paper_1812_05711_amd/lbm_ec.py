@@ -83,6 +83,10 @@ def lib():
     L.lbm_ec_poisson.restype = ctypes.c_int
     L.lbm_ec_stats.argtypes = [vp, dp]
     L.lbm_ec_stats.restype = ctypes.c_int
+    L.lbm_ec_profile_begin.argtypes = [vp]
+    L.lbm_ec_profile_begin.restype = ctypes.c_int
+    L.lbm_ec_profile_end.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    L.lbm_ec_profile_end.restype = ctypes.c_int
     L.lbm_ec_destroy.argtypes = [vp]
     L.lbm_ec_destroy.restype = None
     L.lbm_ec_last_error.argtypes = []
@@ -174,6 +178,19 @@ class Simulation:
             _check(code)
         names = ["steps", "mass_dev", "charge", "rms_uy", "max_u", "min_rho_c", "bad", "max_ex"]
         return dict(zip(names, list(buf))), code == OK
+
+    KERNEL_CLASSES = ("forward", "mean_mode", "tridiag", "inverse", "collide")
+
+    def profile_begin(self):
+        _check(lib().lbm_ec_profile_begin(self._h))
+
+    def profile_end(self):
+        """{class: (total_ms, launches)} since profile_begin (waits for the stream)."""
+        n = len(self.KERNEL_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(lib().lbm_ec_profile_end(self._h, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNEL_CLASSES)}
 
     def close(self):
         if getattr(self, "_h", None):
