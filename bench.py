@@ -32,8 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COLLIDE_BYTES_PER_NODE = {"fp32": 148, "fp64": 296}
-STEP_BYTES_PER_NODE = {"fp32": 176, "fp64": 352}
+COLLIDE_BYTES_PER_NODE = {"fp32": 148, "fp32_f64math": 148, "fp64": 296}
+STEP_BYTES_PER_NODE = {"fp32": 176, "fp32_f64math": 176, "fp64": 352}
 WORKLOAD = dict(T=500.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6,
                 noise_amp=1e-4, seed=181205711)
 
@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--nx", type=int, default=4096)
     ap.add_argument("--ny", type=int, default=4096)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_f64math", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 

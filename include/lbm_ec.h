@@ -53,9 +53,12 @@ enum {
 /* storage precision of the populations */
 enum {
   LBM_EC_FP64 = 0,     /* FP64 storage and arithmetic everywhere */
-  LBM_EC_FP32_DEV = 1  /* FP32 deviations from the hydrostatic reference rows;
+  LBM_EC_FP32_DEV = 1, /* FP32 deviations from the hydrostatic reference rows;
                           FP64 for the x-mean (m = 0) Poisson mode and the
                           reductions */
+  LBM_EC_FP32_DEV_F64MATH = 2 /* FP32_DEV storage and transforms, with the
+                          collision arithmetic in FP64 (loads widened,
+                          results rounded once to FP32 on store) */
 };
 
 /* initial state */
@@ -88,7 +91,7 @@ typedef struct {
                            injected charge C (M K)^2 / ny^2 and D_c = K / Fe */
   double Lambda;        /* fluid TRT product of Eq. 17 (> 0) */
   double Lambda_g;      /* charge TRT product of Eq. 17 (> 0) */
-  int32_t precision;    /* LBM_EC_FP64 or LBM_EC_FP32_DEV */
+  int32_t precision;    /* LBM_EC_FP64, LBM_EC_FP32_DEV or LBM_EC_FP32_DEV_F64MATH */
   int32_t init_mode;    /* LBM_EC_INIT_* */
   double noise_amp;     /* relative charge noise amplitude (INIT_NOISE) */
   uint64_t seed;        /* noise generator seed */

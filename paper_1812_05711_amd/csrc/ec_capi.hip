@@ -79,10 +79,10 @@ ec::FftPlan make_plan(int n) {
 }
 
 struct Layout {
-  int P, M, MP;
+  int P, M, MP, NC;
   size_t tsize;
-  size_t off_f[2], off_g[2], off_phi, off_spec, off_cp, off_tw, off_rows, off_rowsd, off_dmean, off_mom,
-      off_stats, total;
+  size_t off_f[2], off_g[2], off_phi, off_spec, off_tt, off_ends, off_gh, off_iface, off_tw, off_rows,
+      off_rowsd, off_dmean, off_mom, off_stats, total;
 };
 
 Layout make_layout(const lbm_ec_params& p) {
@@ -92,7 +92,8 @@ Layout make_layout(const lbm_ec_params& p) {
   L.P = (p.nx + elems - 1) / elems * elems;
   L.M = p.nx / 2 + 1;
   L.MP = (L.M + elems - 1) / elems * elems;
-  const size_t ny = (size_t)p.ny, nx = (size_t)p.nx;
+  L.NC = (p.ny + ec::kChunk - 1) / ec::kChunk;
+  const size_t ny = (size_t)p.ny, nx = (size_t)p.nx, nc = (size_t)L.NC;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -106,7 +107,10 @@ Layout make_layout(const lbm_ec_params& p) {
   L.off_g[1] = take(pop);
   L.off_phi = take(ny * L.P * L.tsize);
   L.off_spec = take(ny * L.MP * 2 * L.tsize);
-  L.off_cp = take(ny * L.MP * L.tsize);
+  L.off_tt = take(4 * 3 * (size_t)ec::kChunk * L.MP * L.tsize);
+  L.off_ends = take(nc * 2 * L.MP * 2 * L.tsize);
+  L.off_gh = take(nc * 6 * L.MP * L.tsize);
+  L.off_iface = take(nc * 2 * L.MP * 2 * L.tsize);
   L.off_tw = take(nx * 2 * L.tsize);
   L.off_rows = take(ec::ROW_COUNT * ny * L.tsize);
   L.off_rowsd = take(ec::ROWD_COUNT * ny * 8);
@@ -120,7 +124,7 @@ Layout make_layout(const lbm_ec_params& p) {
 int validate(const lbm_ec_params* p) {
   if (!p) return fail(LBM_EC_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 3) return fail(LBM_EC_EINVAL, "grid must have nx >= 1 and ny >= 3");
-  if (p->precision != LBM_EC_FP64 && p->precision != LBM_EC_FP32_DEV)
+  if (p->precision != LBM_EC_FP64 && p->precision != LBM_EC_FP32_DEV && p->precision != LBM_EC_FP32_DEV_F64MATH)
     return fail(LBM_EC_EINVAL, "unknown precision");
   if (p->nx > max_nx(p->precision))
     return fail(LBM_EC_EINVAL, "nx exceeds the x-transform limit (" + std::to_string(max_nx(p->precision)) +
@@ -196,6 +200,7 @@ int setup(lbm_ec* h, unsigned char* ws) {
   c.P = L.P;
   c.M = L.M;
   c.MP = L.MP;
+  c.NC = L.NC;
   c.wp = 1.0 / p.tau_plus;
   c.wm = 1.0 / tau_m;
   c.wgp = 1.0 / tau_gp;
@@ -230,6 +235,7 @@ int setup(lbm_ec* h, unsigned char* ws) {
     const double F0 = eps * p.C * e0 / std::pow(H, 3.0);
     s_ref = 3.0 * F0;
   }
+  c.s_init = 36.0 * round_bits(s_ref / 36.0, 40);
   s_ref = 36.0 * round_bits(s_ref / 36.0, bits);
   std::vector<double> q(ny), rho_ref(ny);
   for (int j = 0; j < ny; ++j) {
@@ -237,10 +243,7 @@ int setup(lbm_ec* h, unsigned char* ws) {
     rho_ref[j] = 1.0 + s_ref * (((double)j + 0.5) - 0.5 * H);
   }
   const double wa = 1.0 / 9.0, wd = 1.0 / 36.0;
-  c.f_up_axis = -wa * s_ref;
-  c.f_up_diag = -wd * s_ref;
-  c.f_dn_axis = wa * s_ref;
-  c.f_dn_diag = wd * s_ref;
+  c.s_ref = s_ref;
   // R_axis = 4 q, R_diag = q (36 w_i is exactly 4 and 1)
   c.g_abb_axis = 2.0 * (wa * rho0 - 4.0 * q[0]);
   c.g_abb_diag = 2.0 * (wd * rho0 - 1.0 * q[0]);
@@ -263,19 +266,46 @@ int setup(lbm_ec* h, unsigned char* ws) {
     rowsd[ec::ROWD_RC_CLOSED * ny + j] = rc_closed[j];
   }
 
-  // elimination factors of the per-wavenumber systems (m >= 1)
-  const int M = L.M, MP = L.MP;
-  std::vector<T> cp((size_t)ny * MP, T(0));
-  for (int m = 1; m < M; ++m) {
-    const int mf = std::min(m, nx - m);
-    const double kap = 2.0 * M_PI * (double)mf / (double)nx;
-    const double b = -(2.0 + kap * kap);
-    double prev = 0.0;
-    for (int j = 0; j < ny; ++j) {
-      const double diag = b - ((j == 0 || j == ny - 1) ? 1.0 : 0.0);
-      const double cpj = j == 0 ? 1.0 / diag : 1.0 / (diag - prev);
-      cp[(size_t)j * MP + m] = (T)cpj;
-      prev = cpj;
+  // chunk tables of the per-wavenumber y systems (m >= 1): for each chunk
+  // type the elimination factors of its own system and its responses v, w
+  // to unit values just below / just above it (FP64, then rounded to T)
+  const int M = L.M, MP = L.MP, NC = L.NC;
+  const int KC = ec::kChunk;
+  std::vector<T> tt((size_t)4 * 3 * KC * MP, T(0));
+  auto tidx = [&](int type, int q, int i, int m) { return ((size_t)(type * 3 + q) * KC + i) * MP + m; };
+  for (int type = 0; type < 4; ++type) {
+    int len;
+    if (type == ec::CH_SINGLE) {
+      if (NC != 1) continue;
+      len = ny;
+    } else {
+      if (NC == 1) continue;
+      if (type == ec::CH_INTERIOR && NC < 3) continue;
+      len = type == ec::CH_LAST ? ny - (NC - 1) * KC : KC;
+    }
+    const bool wall_lo = type == ec::CH_SINGLE || type == ec::CH_FIRST;
+    const bool wall_hi = type == ec::CH_SINGLE || type == ec::CH_LAST;
+    std::vector<double> cpv(len), rhs(len), dp(len), x(len);
+    for (int m = 1; m < M; ++m) {
+      const int mf = std::min(m, nx - m);
+      const double kap = 2.0 * M_PI * (double)mf / (double)nx;
+      const double b = -(2.0 + kap * kap);
+      for (int i = 0; i < len; ++i) {
+        const double diag = b - ((i == 0 && wall_lo) ? 1.0 : 0.0) - ((i == len - 1 && wall_hi) ? 1.0 : 0.0);
+        cpv[i] = i == 0 ? 1.0 / diag : 1.0 / (diag - cpv[i - 1]);
+        tt[tidx(type, 0, i, m)] = (T)cpv[i];
+      }
+      // responses: A v = -e_0 (value just below), A w = -e_{len-1} (just above)
+      for (int q = 1; q <= 2; ++q) {
+        if (q == 1 && wall_lo) continue;
+        if (q == 2 && wall_hi) continue;
+        for (int i = 0; i < len; ++i) rhs[i] = 0.0;
+        rhs[q == 1 ? 0 : len - 1] = -1.0;
+        for (int i = 0; i < len; ++i) dp[i] = (rhs[i] - (i ? dp[i - 1] : 0.0)) * cpv[i];
+        x[len - 1] = dp[len - 1];
+        for (int i = len - 2; i >= 0; --i) x[i] = dp[i] - cpv[i] * x[i + 1];
+        for (int i = 0; i < len; ++i) tt[tidx(type, q, i, m)] = (T)x[i];
+      }
     }
   }
   // twiddles exp(-2 pi i k / nx)
@@ -287,7 +317,8 @@ int setup(lbm_ec* h, unsigned char* ws) {
   }
   EC_HIP(hipMemcpyAsync(h->b.rows, rows.data(), rows.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.rowsd, rowsd.data(), rowsd.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
-  EC_HIP(hipMemcpyAsync(h->b.cp, cp.data(), cp.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.tt, tt.data(), tt.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipMemsetAsync(h->b.iface, 0, (size_t)NC * 2 * MP * 2 * sizeof(T), h->s));
   EC_HIP(hipMemcpyAsync(h->b.tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemsetAsync(ws + L.off_spec, 0, (size_t)ny * MP * 2 * sizeof(T), h->s));
   EC_HIP(hipMemsetAsync(ws + L.off_phi, 0, (size_t)ny * L.P * sizeof(T), h->s));
@@ -329,7 +360,7 @@ int poisson_chain(lbm_ec* h, int mode, int src) {
   return LBM_EC_OK;
 }
 
-template <typename T>
+template <typename T, typename C>
 int init_state(lbm_ec* h) {
   int rc;
   // initial charge, its potential, the equilibria into buffer 1
@@ -339,19 +370,19 @@ int init_state(lbm_ec* h) {
   // step 0: charge of the initial populations, Poisson, first collision
   // (no streaming) into buffer 0, with the moments of state 0
   if ((rc = poisson_chain<T>(h, 1, 1))) return rc;
-  EC_HIP(ec::launch_collide<T>(h->c, h->b, false, true, 1, 0, h->s));
+  EC_HIP((ec::launch_collide<T, C>(h->c, h->b, false, true, 1, 0, h->s)));
   h->cur = 0;
   h->steps = 0;
   return LBM_EC_OK;
 }
 
-template <typename T>
+template <typename T, typename C>
 int run_steps(lbm_ec* h, int64_t n) {
   int rc;
   for (int64_t k = 0; k < n; ++k) {
     const int src = h->cur, dst = 1 - h->cur;
     if ((rc = poisson_chain<T>(h, 0, src))) return rc;
-    EC_TIMED(h, KC_COLLIDE, (ec::launch_collide<T>(h->c, h->b, true, k == n - 1, src, dst, h->s)));
+    EC_TIMED(h, KC_COLLIDE, (ec::launch_collide<T, C>(h->c, h->b, true, k == n - 1, src, dst, h->s)));
     h->cur = dst;
     h->steps += 1;
   }
@@ -406,7 +437,7 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
   h->p = *p;
   h->L = L;
   h->s = (hipStream_t)hip_stream;
-  h->fp32 = p->precision == LBM_EC_FP32_DEV;
+  h->fp32 = p->precision != LBM_EC_FP64;
   h->plan = make_plan(p->nx);
   unsigned char* ws = (unsigned char*)d_ws;
   h->b.f[0] = ws + L.off_f[0];
@@ -415,7 +446,10 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
   h->b.g[1] = ws + L.off_g[1];
   h->b.phi = ws + L.off_phi;
   h->b.spec = ws + L.off_spec;
-  h->b.cp = ws + L.off_cp;
+  h->b.tt = ws + L.off_tt;
+  h->b.ends = ws + L.off_ends;
+  h->b.gh = ws + L.off_gh;
+  h->b.iface = ws + L.off_iface;
   h->b.tw = ws + L.off_tw;
   h->b.rows = ws + L.off_rows;
   h->b.rowsd = (double*)(ws + L.off_rowsd);
@@ -423,7 +457,14 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
   h->b.mom = (double*)(ws + L.off_mom);
   h->b.stats = (double*)(ws + L.off_stats);
   rc = h->fp32 ? setup<float>(h, ws) : setup<double>(h, ws);
-  if (!rc) rc = h->fp32 ? init_state<float>(h) : init_state<double>(h);
+  if (!rc) {
+    if (p->precision == LBM_EC_FP64)
+      rc = init_state<double, double>(h);
+    else if (p->precision == LBM_EC_FP32_DEV)
+      rc = init_state<float, float>(h);
+    else
+      rc = init_state<float, double>(h);
+  }
   if (!rc) {
     hipError_t e = hipStreamSynchronize(h->s);
     if (e != hipSuccess) rc = fail(LBM_EC_EHIP, std::string("initial state: ") + hipGetErrorString(e));
@@ -439,7 +480,9 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
 int lbm_ec_step(lbm_ec_t* h, int64_t n) {
   if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
   if (n < 0) return fail(LBM_EC_EINVAL, "negative step count");
-  return h->fp32 ? run_steps<float>(h, n) : run_steps<double>(h, n);
+  if (h->p.precision == LBM_EC_FP64) return run_steps<double, double>(h, n);
+  if (h->p.precision == LBM_EC_FP32_DEV) return run_steps<float, float>(h, n);
+  return run_steps<float, double>(h, n);
 }
 
 int64_t lbm_ec_steps_done(const lbm_ec_t* h) { return h ? h->steps : -1; }

@@ -17,6 +17,12 @@ struct FftPlan {
   int r[kMaxRadices];
 };
 
+// Rows per chunk of the partitioned per-wavenumber solves.
+constexpr int kChunk = 32;
+// Chunk types: the whole column (one chunk), the first one (lower electrode
+// ghost row), an interior one, the last one (upper electrode ghost row).
+enum ChunkType { CH_SINGLE = 0, CH_FIRST = 1, CH_INTERIOR = 2, CH_LAST = 3 };
+
 // Scalar constants of one instance, in lattice units (see the public header
 // for the unit conventions).  Kernels convert to their storage type.
 struct Consts {
@@ -24,15 +30,22 @@ struct Consts {
   int P;       // row pitch of node arrays, elements
   int M;       // number of non-negative x wavenumbers, nx/2 + 1
   int MP;      // row pitch of spectral arrays, elements
+  int NC;      // number of y chunks, ceil(ny / kChunk)
   double wp, wm, wgp, wgm;  // TRT rates: fluid +/-, charge +/-
   double K;                 // ion mobility
   double eps;               // permittivity
   double bx;                // body force density along x
   double H;                 // electrode gap (= ny)
   double u0;                // velocity unit K / H
-  // re-reference of f on y-streaming: arrivals from the row below
-  // (c_iy = +1) and from the row above (c_iy = -1), axis / diagonal weights
-  double f_up_axis, f_up_diag, f_dn_axis, f_dn_diag;
+  // slope s of the reference density rho_ref(y) = 1 + s (y - H/2); the
+  // reference force s/3 balances it.  The fluid populations are stored as
+  // deviations from f_ref,i = w_i (rho_ref - (s/2) c_iy) before collision and
+  // from w_i (rho_ref + (s/2) c_iy) after it, the exact fixed point of the
+  // forced TRT step with halfway bounce-back for that density and force.
+  double s_ref;
+  // slope of the initial density profile, 1 + s_init (y - H/2); the same in
+  // every precision (s_ref is rounded coarser for FP32 storage)
+  double s_init;
   // injector anti-bounce-back constants 2 (w_i rho0 - R_i(0)) on deviations
   double g_abb_axis, g_abb_diag;
   // initial state
@@ -60,6 +73,7 @@ enum RowTableD {
   ROWD_DCSUM,        // sum over x of the charge deviation (written each step)
   ROWD_EYM,          // x-mean field E_y(j) (written each step)
   ROWD_PHIM,         // x-mean potential (written each step)
+  ROWD_DFY,          // r(j) E_y mean(j) - s/3: x-mean force less the reference force
   ROWD_COUNT
 };
 
@@ -68,8 +82,12 @@ struct Bufs {
   void* f[2];    // [9][ny][P] populations (deviations), ping-pong
   void* g[2];
   void* phi;     // [ny][P] potential fluctuation (m >= 1 modes)
-  void* spec;    // [ny][MP] complex spectrum (forward, solved in place)
-  void* cp;      // [ny][MP] Thomas elimination factors, per wavenumber
+  void* spec;    // [ny][MP] complex spectrum (forward, then chunk solutions in place)
+  void* tt;      // [4 types][3: cp, v, w][kChunk][MP] chunk tables of the y solves
+  void* ends;    // [P][2][MP] complex: first / last row of each chunk's local solution
+  void* gh;      // [P][6][MP]: block-elimination scratch of the interface system
+  void* iface;   // [P][2][MP] complex: interface values a_k (last row of chunk k),
+                 //                      b_k (first row of chunk k+1)
   void* tw;      // [nx] complex twiddles exp(-2 pi i k / nx)
   void* rows;    // ROW_COUNT x [ny]
   double* rowsd; // ROWD_COUNT x [ny]
@@ -91,11 +109,14 @@ hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int
                           hipStream_t s);
 template <typename T>
 hipError_t launch_mean_mode(const Consts& c, const Bufs& b, hipStream_t s);
+// per-wavenumber y solves, m >= 1: chunk-local solves, then the interface
+// system (the chunk corrections are applied by launch_inverse)
 template <typename T>
 hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s);
 template <typename T>
 hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, hipStream_t s);
-template <typename T>
+// T: storage type of the populations, C: arithmetic type of the collision
+template <typename T, typename C>
 hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst,
                           hipStream_t s);
 template <typename T>

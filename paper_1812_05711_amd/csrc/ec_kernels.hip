@@ -271,7 +271,8 @@ __device__ __forceinline__ void pull_g(const Consts& c, const T* __restrict__ G,
 }
 
 // Pre-collision fluid populations at (x, j) with halfway bounce-back at both
-// electrodes (Table I) and the re-reference of rows crossed.
+// electrodes (Table I).  On the deviations from the hydrostatic fixed point
+// neither the row crossings nor the walls add a constant.
 template <typename T>
 __device__ __forceinline__ void pull_f(const Consts& c, const T* __restrict__ F, int x, int j, T f[9]) {
   const size_t plane = (size_t)c.ny * c.P;
@@ -282,9 +283,9 @@ __device__ __forceinline__ void pull_f(const Consts& c, const T* __restrict__ F,
   f[3] = F[3 * plane + row + xp];
   if (j > 0) {
     const size_t rb = row - c.P;
-    f[2] = F[2 * plane + rb + x] + T(c.f_up_axis);
-    f[5] = F[5 * plane + rb + xm] + T(c.f_up_diag);
-    f[6] = F[6 * plane + rb + xp] + T(c.f_up_diag);
+    f[2] = F[2 * plane + rb + x];
+    f[5] = F[5 * plane + rb + xm];
+    f[6] = F[6 * plane + rb + xp];
   } else {
     f[2] = F[4 * plane + row + x];
     f[5] = F[7 * plane + row + x];
@@ -292,9 +293,9 @@ __device__ __forceinline__ void pull_f(const Consts& c, const T* __restrict__ F,
   }
   if (j < c.ny - 1) {
     const size_t ra = row + c.P;
-    f[4] = F[4 * plane + ra + x] + T(c.f_dn_axis);
-    f[7] = F[7 * plane + ra + xp] + T(c.f_dn_diag);
-    f[8] = F[8 * plane + ra + xm] + T(c.f_dn_diag);
+    f[4] = F[4 * plane + ra + x];
+    f[7] = F[7 * plane + ra + xp];
+    f[8] = F[8 * plane + ra + xm];
   } else {
     f[4] = F[2 * plane + row + x];
     f[7] = F[5 * plane + row + x];
@@ -436,41 +437,164 @@ __global__ void __launch_bounds__(1024) k_mean_mode(Consts c, double* __restrict
   const double phi0 = 1.0 + 0.5 * dlow;
   double* eym = rowsd + ROWD_EYM * ny;
   double* phim = rowsd + ROWD_PHIM * ny;
+  double* dfy = rowsd + ROWD_DFY * ny;
   if (threadIdx.x == 0) dmean[0] = dlow;
   for (int j = lo; j < hi; ++j) {
     const double Dj = dmean[1 + j];
     const double Djm = j > 0 ? dmean[j] : dlow;
     phim[j] = phi0 + run;
-    eym[j] = -(Dj + Djm) / 2.0;
+    const double e = -(Dj + Djm) / 2.0;
+    eym[j] = e;
+    dfy[j] = r[j] * e - c.s_ref / 3.0;
     run += Dj;
   }
 }
 
 // ------------------------------------------------- per-wavenumber solves
 // m = 1 .. nx/2: phi(j+1) - (2 + kappa_m^2) phi(j) + phi(j-1) = s(j) with
-// homogeneous ghost closures (Eq. 20, 24-25 as a tridiagonal per m), by
-// elimination with the precomputed factors cp = 1 / (b_j - cp_{j-1}).
+// homogeneous ghost closures (Eq. 20, 24-25 as a tridiagonal per m), solved
+// by partition: the column splits into chunks of kChunk rows; in chunk k the
+// solution is x = y + v L_k + w R_k, where y solves the chunk's own system
+// with zero values outside it, v and w are the chunk's responses to unit
+// values in the row just below (L_k) and just above (R_k), and L_k, R_k come
+// from a 2x2 block-tridiagonal system over the chunk interfaces.
+
+__device__ __forceinline__ int chunk_type(int k, int nc) {
+  return nc == 1 ? CH_SINGLE : (k == 0 ? CH_FIRST : (k == nc - 1 ? CH_LAST : CH_INTERIOR));
+}
+
+// Table q (0 elimination factors, 1 v, 2 w) of a chunk type, row i, wavenumber m.
 template <typename T>
-__global__ void __launch_bounds__(64) k_tridiag(Consts c, const T* __restrict__ cp, C2<T>* __restrict__ spec) {
+__device__ __forceinline__ T ttab(const T* __restrict__ tt, int MP, int type, int q, int i, int m) {
+  return tt[((size_t)(type * 3 + q) * kChunk + i) * MP + m];
+}
+
+// One thread per (m, chunk): elimination and back substitution of the
+// chunk's own system in registers; y overwrites the spectrum, its first and
+// last rows go to `ends`.
+template <typename T>
+__global__ void __launch_bounds__(64) k_tri_local(Consts c, const T* __restrict__ tt, C2<T>* __restrict__ spec,
+                                                  C2<T>* __restrict__ ends) {
+  const int m = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (m >= c.M) return;
+  const int s0 = k * kChunk;
+  const int len = min(kChunk, c.ny - s0);
+  const int type = chunk_type(k, c.NC);
+  const size_t MP = c.MP;
+  C2<T> d[kChunk];
+  C2<T> prev = {T(0), T(0)};
+#pragma unroll
+  for (int i = 0; i < kChunk; ++i) {
+    if (i < len) {
+      const T f = ttab(tt, c.MP, type, 0, i, m);
+      const C2<T> sv = spec[(s0 + i) * MP + m];
+      prev = C2<T>{(sv.re - prev.re) * f, (sv.im - prev.im) * f};
+      d[i] = prev;
+    }
+  }
+  C2<T> x = {T(0), T(0)}, first = {T(0), T(0)}, last = {T(0), T(0)};
+#pragma unroll
+  for (int i = kChunk - 1; i >= 0; --i) {
+    if (i < len) {
+      if (i == len - 1) {
+        x = d[i];
+        last = x;
+      } else {
+        const T f = ttab(tt, c.MP, type, 0, i, m);
+        x = C2<T>{d[i].re - f * x.re, d[i].im - f * x.im};
+      }
+      spec[(s0 + i) * MP + m] = x;
+    }
+  }
+  first = x;
+  ends[(2 * (size_t)k) * MP + m] = first;
+  ends[(2 * (size_t)k + 1) * MP + m] = last;
+}
+
+// One thread per m: the interface system.  Interface k (between chunks k
+// and k+1) carries a_k = x(last row of chunk k) and b_k = x(first row of
+// chunk k+1):
+//   a_k - v_e(k) a_{k-1} - w_e(k) b_k       = y_e(k)
+//   b_k - v_s(k+1) a_k   - w_s(k+1) b_{k+1} = y_s(k+1)
+// (v_s, v_e, w_s, w_e: first / last entries of the chunk responses), solved
+// by block elimination with 2x2 pivots [[1, beta], [gamma, 1]].
+template <typename T>
+__global__ void __launch_bounds__(64) k_tri_reduced(Consts c, const T* __restrict__ tt, const C2<T>* __restrict__ ends,
+                                                    T* __restrict__ gh, C2<T>* __restrict__ iface) {
   const int m = 1 + blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= c.M) return;
+  const int nc = c.NC;
+  if (nc < 2) return;
   const size_t MP = c.MP;
-  C2<T> dprev = {T(0), T(0)};
-  for (int j = 0; j < c.ny; ++j) {
-    const T f = cp[j * MP + m];
-    const C2<T> s = spec[j * MP + m];
-    const C2<T> d = {(s.re - dprev.re) * f, (s.im - dprev.im) * f};
-    spec[j * MP + m] = d;
-    dprev = d;
+  T g01_prev = T(0);
+  C2<T> h0_prev = {T(0), T(0)};
+  for (int k = 0; k < nc - 1; ++k) {
+    const int tk = chunk_type(k, nc), tn = chunk_type(k + 1, nc);
+    const int lenk = min(kChunk, c.ny - k * kChunk);
+    const int lenn = min(kChunk, c.ny - (k + 1) * kChunk);
+    const T ve = ttab(tt, c.MP, tk, 1, lenk - 1, m);
+    const T we = ttab(tt, c.MP, tk, 2, lenk - 1, m);
+    const T vs = ttab(tt, c.MP, tn, 1, 0, m);
+    const T ws = ttab(tt, c.MP, tn, 2, 0, m);
+    (void)lenn;
+    const C2<T> ye = ends[(2 * (size_t)k + 1) * MP + m];
+    const C2<T> ys = ends[(2 * (size_t)(k + 1)) * MP + m];
+    const T beta = -we + ve * g01_prev;
+    const T gamma = -vs;
+    const T inv = T(1) / (T(1) - beta * gamma);
+    const C2<T> D0 = {ye.re + ve * h0_prev.re, ye.im + ve * h0_prev.im};
+    const C2<T> D1 = ys;
+    const C2<T> H0 = {(D0.re - beta * D1.re) * inv, (D0.im - beta * D1.im) * inv};
+    const C2<T> H1 = {(D1.re - gamma * D0.re) * inv, (D1.im - gamma * D0.im) * inv};
+    const T g01 = beta * ws * inv;
+    const T g11 = -ws * inv;
+    T* q = gh + (6 * (size_t)k) * MP + m;
+    q[0] = g01;
+    q[MP] = g11;
+    q[2 * MP] = H0.re;
+    q[3 * MP] = H0.im;
+    q[4 * MP] = H1.re;
+    q[5 * MP] = H1.im;
+    g01_prev = g01;
+    h0_prev = H0;
   }
-  C2<T> xn = dprev;
-  for (int j = c.ny - 2; j >= 0; --j) {
-    const T f = cp[j * MP + m];
-    const C2<T> d = spec[j * MP + m];
-    const C2<T> xv = {d.re - f * xn.re, d.im - f * xn.im};
-    spec[j * MP + m] = xv;
-    xn = xv;
+  C2<T> bnext = {T(0), T(0)};
+  for (int k = nc - 2; k >= 0; --k) {
+    const T* q = gh + (6 * (size_t)k) * MP + m;
+    const T g01 = q[0], g11 = q[MP];
+    const C2<T> a = {q[2 * MP] - g01 * bnext.re, q[3 * MP] - g01 * bnext.im};
+    const C2<T> b = {q[4 * MP] - g11 * bnext.re, q[5 * MP] - g11 * bnext.im};
+    iface[(2 * (size_t)k) * MP + m] = a;
+    iface[(2 * (size_t)k + 1) * MP + m] = b;
+    bnext = b;
   }
+}
+
+// Solution of row j, wavenumber m: the chunk-local y (in spec) plus the
+// responses to the interface values.
+template <typename T>
+__device__ __forceinline__ C2<T> solved_mode(const Consts& c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
+                                             const C2<T>* __restrict__ iface, int j, int m) {
+  C2<T> y = spec[(size_t)j * c.MP + m];
+  if (c.NC > 1) {
+    const int k = j / kChunk, i = j - k * kChunk;
+    const int type = chunk_type(k, c.NC);
+    const size_t MP = c.MP;
+    if (k > 0) {
+      const T v = ttab(tt, c.MP, type, 1, i, m);
+      const C2<T> L = iface[(2 * (size_t)(k - 1)) * MP + m];
+      y.re += v * L.re;
+      y.im += v * L.im;
+    }
+    if (k < c.NC - 1) {
+      const T w = ttab(tt, c.MP, type, 2, i, m);
+      const C2<T> R = iface[(2 * (size_t)k + 1) * MP + m];
+      y.re += w * R.re;
+      y.im += w * R.im;
+    }
+  }
+  return y;
 }
 
 // --------------------------------------------------- inverse transform
@@ -478,7 +602,8 @@ __global__ void __launch_bounds__(64) k_tridiag(Consts c, const T* __restrict__ 
 // two solved spectra (m = 0 left out: it lives in the x-mean row), inverse
 // transform, 1/nx, real / imaginary parts to the two rows of phi.
 template <typename T>
-__global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restrict__ spec, FftPlan pl,
+__global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
+                                                 const C2<T>* __restrict__ iface, FftPlan pl,
                                                  const C2<T>* __restrict__ tw, T* __restrict__ phi) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* a = reinterpret_cast<C2<T>*>(smem);
@@ -491,8 +616,8 @@ __global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restri
     if (m > 0) {
       const bool lowh = m < c.M;
       const int mm = lowh ? m : N - m;
-      C2<T> X = spec[(size_t)j0 * c.MP + mm];
-      C2<T> Y = has1 ? spec[(size_t)j1 * c.MP + mm] : C2<T>{T(0), T(0)};
+      C2<T> X = solved_mode<T>(c, spec, tt, iface, j0, mm);
+      C2<T> Y = has1 ? solved_mode<T>(c, spec, tt, iface, j1, mm) : C2<T>{T(0), T(0)};
       if (!lowh) {
         X.im = -X.im;
         Y.im = -Y.im;
@@ -517,7 +642,7 @@ __global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restri
 // Then the moments (Eq. 5-7), E = -grad phi (central differences, the mean
 // row in FP64), the equilibria (Eq. 10-11), the source (Eq. 12) and the TRT
 // collisions (Eq. 8-9, 13-15); writes the post-collision deviations.
-template <typename T, bool PULL, bool EMIT>
+template <typename T, typename C, bool PULL, bool EMIT>
 __global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__ Fin, const T* __restrict__ Gin,
                                                  T* __restrict__ Fout, T* __restrict__ Gout,
                                                  const T* __restrict__ phi, const T* __restrict__ rows,
@@ -525,36 +650,49 @@ __global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= c.nx || j >= c.ny) return;
-  T f[9], g[9];
-  if (PULL) {
-    pull_f<T>(c, Fin, x, j, f);
-    pull_g<T>(c, Gin, rows, x, j, g);
-  } else {
-    local_pop<T>(c, Fin, x, j, f);
-    local_pop<T>(c, Gin, x, j, g);
+  C f[9], g[9];
+  {
+    T ft[9], gt[9];
+    if (PULL) {
+      pull_f<T>(c, Fin, x, j, ft);
+      pull_g<T>(c, Gin, rows, x, j, gt);
+    } else {
+      local_pop<T>(c, Fin, x, j, ft);
+      local_pop<T>(c, Gin, x, j, gt);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f[i] = (C)ft[i];
+      g[i] = (C)gt[i];
+    }
   }
   // moments
-  const T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  const T rho = rows[ROW_RHO_REF * c.ny + j] + drho;
-  const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  const T drc = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-  const T rc = rows[ROW_R * c.ny + j] + drc;
+  const C drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const C rho = (C)rows[ROW_RHO_REF * c.ny + j] + drho;
+  const C jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  const C jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  const C drc = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+  const C rc = (C)rows[ROW_R * c.ny + j] + drc;
   // electric field
   const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
   const size_t row = (size_t)j * c.P;
-  const T pc = phi[row + x];
-  const T pxp = phi[row + xp], pxm = phi[row + xm];
-  const T pyp = j < c.ny - 1 ? phi[row + c.P + x] : -pc;
-  const T pym = j > 0 ? phi[row - c.P + x] : -pc;
-  const T ex = -(pxp - pxm) / T(2);
-  const T ey = T(rowsd[ROWD_EYM * c.ny + j]) - (pyp - pym) / T(2);
-  const T fx = rc * ex + T(c.bx);
-  const T fy = rc * ey;
-  const T ux = (jx + T(0.5) * fx) / rho;
-  const T uy = (jy + T(0.5) * fy) / rho;
-  const T vx = ux + T(c.K) * ex;
-  const T vy = uy + T(c.K) * ey;
+  const C pc = (C)phi[row + x];
+  const C pxp = (C)phi[row + xp], pxm = (C)phi[row + xm];
+  const C pyp = j < c.ny - 1 ? (C)phi[row + c.P + x] : -pc;
+  const C pym = j > 0 ? (C)phi[row - c.P + x] : -pc;
+  const C ex = -(pxp - pxm) / C(2);
+  const C eyf = -(pyp - pym) / C(2);  // transverse-mode part of E_y
+  const C ey = C(rowsd[ROWD_EYM * c.ny + j]) + eyf;
+  const C fx = rc * ex + C(c.bx);
+  // y force less the reference force s/3, without forming the large terms:
+  // rho_c E_y - s/3 = (r E_y,mean - s/3) + r E_y,fluct + (rho_c - r) E_y
+  const C dfy = C(rowsd[ROWD_DFY * c.ny + j]) + (C)rows[ROW_R * c.ny + j] * eyf + drc * ey;
+  const C fy = C(c.s_ref / 3.0) + dfy;
+  // Eq. 7 on the deviations: sum_i c_i f_ref,i = -(s/6) y-hat cancels s/3 / 2
+  const C ux = (jx + C(0.5) * fx) / rho;
+  const C uy = (jy + C(0.5) * dfy) / rho;
+  const C vx = ux + C(c.K) * ex;
+  const C vy = uy + C(c.K) * ey;
   if (EMIT) {
     const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
     mom[k] = (double)drho;
@@ -562,50 +700,53 @@ __global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__
     mom[2 * n + k] = (double)uy;
     mom[3 * n + k] = (double)drc;
   }
-  const T w0 = T(4.0 / 9.0), wa = T(1.0 / 9.0), wd = T(1.0 / 36.0);
-  const T uu = ux * ux + uy * uy;
-  const T vv = vx * vx + vy * vy;
+  const C w0 = C(4.0 / 9.0), wa = C(1.0 / 9.0), wd = C(1.0 / 36.0);
+  const C uu = ux * ux + uy * uy;
+  const C vv = vx * vx + vy * vy;
   // f^eq_i - w_i rho_ref = w_i drho + w_i rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
-  // F_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F
+  // F_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F; its part 3 w_i c_iy s/3 is
+  // carried by the reference, so the source on the deviations uses
+  // 3 c.(F - s/3 y-hat) in place of 3 c.F
   // charge: g^eq_i - R_i = w_i drc + w_i rc (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)
-  const T wp = T(c.wp), wm = T(c.wm), wgp = T(c.wgp), wgm = T(c.wgm);
-  const T sp = T(1) - T(0.5) * wp, sm = T(1) - T(0.5) * wm;
-  const T uF = ux * fx + uy * fy;
-  T fo[9], go[9];
+  const C wp = C(c.wp), wm = C(c.wm), wgp = C(c.wgp), wgm = C(c.wgm);
+  const C sp = C(1) - C(0.5) * wp, sm = C(1) - C(0.5) * wm;
+  const C uF = ux * fx + uy * fy;
+  C fo[9], go[9];
   {  // rest direction
-    const T feq0 = w0 * drho + w0 * rho * (-T(1.5) * uu);
-    const T F0 = w0 * (-T(3) * uF);
+    const C feq0 = w0 * drho + w0 * rho * (-C(1.5) * uu);
+    const C F0 = w0 * (-C(3) * uF);
     fo[0] = f[0] - wp * (f[0] - feq0) + sp * F0;
-    const T geq0 = w0 * drc + w0 * rc * (-T(1.5) * vv);
+    const C geq0 = w0 * drc + w0 * rc * (-C(1.5) * vv);
     go[0] = g[0] - wgp * (g[0] - geq0);
   }
   // pairs (i, opp): (1,3), (2,4), (5,7), (6,8)
   const int pi[4] = {1, 2, 5, 6}, po[4] = {3, 4, 7, 8};
-  const T cxs[4] = {T(1), T(0), T(1), T(-1)}, cys[4] = {T(0), T(1), T(1), T(1)};
+  const C cxs[4] = {C(1), C(0), C(1), C(-1)}, cys[4] = {C(0), C(1), C(1), C(1)};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = pi[q], o = po[q];
-    const T w = q < 2 ? wa : wd;
-    const T cx = cxs[q], cy = cys[q];
-    const T cu = cx * ux + cy * uy;
-    const T cv = cx * vx + cy * vy;
-    const T cF = cx * fx + cy * fy;
+    const C w = q < 2 ? wa : wd;
+    const C cx = cxs[q], cy = cys[q];
+    const C cu = cx * ux + cy * uy;
+    const C cv = cx * vx + cy * vy;
+    const C cF = cx * fx + cy * fy;
+    const C cdF = cx * fx + cy * dfy;
     // equilibria at i (c) and at opp (-c)
-    const T fe_i = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
-    const T fe_o = w * drho + w * rho * (-T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
-    const T Fs_i = w * (T(3) * (cF - uF) + T(9) * cu * cF);
-    const T Fs_o = w * (T(3) * (-cF - uF) + T(9) * cu * cF);
-    const T ge_i = w * drc + w * rc * (T(3) * cv + T(4.5) * cv * cv - T(1.5) * vv);
-    const T ge_o = w * drc + w * rc * (-T(3) * cv + T(4.5) * cv * cv - T(1.5) * vv);
-    const T fp = T(0.5) * (f[i] + f[o]), fm = T(0.5) * (f[i] - f[o]);
-    const T ep = T(0.5) * (fe_i + fe_o), em = T(0.5) * (fe_i - fe_o);
-    const T Sp = T(0.5) * (Fs_i + Fs_o), Sm = T(0.5) * (Fs_i - Fs_o);
-    const T relp = wp * (fp - ep), relm = wm * (fm - em);
+    const C fe_i = w * drho + w * rho * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu);
+    const C fe_o = w * drho + w * rho * (-C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu);
+    const C Fs_i = w * (C(3) * (cdF - uF) + C(9) * cu * cF);
+    const C Fs_o = w * (C(3) * (-cdF - uF) + C(9) * cu * cF);
+    const C ge_i = w * drc + w * rc * (C(3) * cv + C(4.5) * cv * cv - C(1.5) * vv);
+    const C ge_o = w * drc + w * rc * (-C(3) * cv + C(4.5) * cv * cv - C(1.5) * vv);
+    const C fp = C(0.5) * (f[i] + f[o]), fm = C(0.5) * (f[i] - f[o]);
+    const C ep = C(0.5) * (fe_i + fe_o), em = C(0.5) * (fe_i - fe_o);
+    const C Sp = C(0.5) * (Fs_i + Fs_o), Sm = C(0.5) * (Fs_i - Fs_o);
+    const C relp = wp * (fp - ep), relm = wm * (fm - em);
     fo[i] = f[i] - relp - relm + sp * Sp + sm * Sm;
     fo[o] = f[o] - relp + relm + sp * Sp - sm * Sm;
-    const T gp = T(0.5) * (g[i] + g[o]), gm = T(0.5) * (g[i] - g[o]);
-    const T hp = T(0.5) * (ge_i + ge_o), hm = T(0.5) * (ge_i - ge_o);
-    const T grp = wgp * (gp - hp), grm = wgm * (gm - hm);
+    const C gp = C(0.5) * (g[i] + g[o]), gm = C(0.5) * (g[i] - g[o]);
+    const C hp = C(0.5) * (ge_i + ge_o), hm = C(0.5) * (ge_i - ge_o);
+    const C grp = wgp * (gp - hp), grm = wgm * (gm - hm);
     go[i] = g[i] - grp - grm;
     go[o] = g[o] - grp + grm;
   }
@@ -613,8 +754,8 @@ __global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__
   const size_t idx = row + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    Fout[i * plane + idx] = fo[i];
-    Gout[i * plane + idx] = go[i];
+    Fout[i * plane + idx] = (T)fo[i];
+    Gout[i * plane + idx] = (T)go[i];
   }
 }
 
@@ -657,7 +798,10 @@ __global__ void __launch_bounds__(256) k_init_populations(Consts c, T* __restric
   const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
   const double drc = mom[3 * n + k];
   const double rc = rowsd[ROWD_R * c.ny + j] + drc;
-  const double rho = rowsd[ROWD_RHO_REF * c.ny + j];
+  // initial density 1 + s_init (y - H/2); its difference from the reference row
+  const double yc = ((double)j + 0.5) - 0.5 * c.H;
+  const double rho = 1.0 + c.s_init * yc;
+  const double drho0 = (c.s_init - c.s_ref) * yc;
   double ux = 0.0, uy = 0.0;
   if (c.init_mode == 1) {
     const double twopi = 6.283185307179586;
@@ -684,7 +828,9 @@ __global__ void __launch_bounds__(256) k_init_populations(Consts c, T* __restric
   for (int i = 0; i < 9; ++i) {
     const double cu = cxv[i] * ux + cyv[i] * uy;
     const double cv = cxv[i] * vx + cyv[i] * vy;
-    const double fe = wv[i] * 0.0 + wv[i] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    // f^0 = w_i rho_init (1 + ...) less f_ref = w_i (rho_ref - (s/2) c_iy)
+    const double fe = wv[i] * drho0 + wv[i] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu) +
+                      0.5 * c.s_ref * wv[i] * cyv[i];
     const double ge = wv[i] * drc + wv[i] * rc * (3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
     F[i * plane + row + x] = (T)fe;
     G[i * plane + row + x] = (T)ge;
@@ -821,7 +967,12 @@ template <typename T>
 hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
   const int nm = c.M - 1;
   if (nm <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tridiag<T>, dim3((nm + 63) / 64), dim3(64), 0, s, c, (const T*)b.cp, (C2<T>*)b.spec);
+  hipLaunchKernelGGL(k_tri_local<T>, dim3((nm + 63) / 64, c.NC), dim3(64), 0, s, c, (const T*)b.tt,
+                     (C2<T>*)b.spec, (C2<T>*)b.ends);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || c.NC < 2) return e;
+  hipLaunchKernelGGL(k_tri_reduced<T>, dim3((nm + 63) / 64), dim3(64), 0, s, c, (const T*)b.tt,
+                     (const C2<T>*)b.ends, (T*)b.gh, (C2<T>*)b.iface);
   return hipGetLastError();
 }
 
@@ -829,11 +980,12 @@ template <typename T>
 hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, hipStream_t s) {
   dim3 blk(256), grd((c.ny + 1) / 2);
   const size_t lds = fft_lds_bytes<T>(pl.n);
-  hipLaunchKernelGGL(k_inverse<T>, grd, blk, lds, s, c, (const C2<T>*)b.spec, pl, (const C2<T>*)b.tw, (T*)b.phi);
+  hipLaunchKernelGGL(k_inverse<T>, grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
+                     (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename C>
 hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst, hipStream_t s) {
   dim3 blk(64, 4);
   dim3 grd = node_grid2(c, blk);
@@ -844,13 +996,13 @@ hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, 
   const T* phi = (const T*)b.phi;
   const T* rows = (const T*)b.rows;
   if (pull && emit)
-    hipLaunchKernelGGL((k_collide<T, true, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, true, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
   else if (pull)
-    hipLaunchKernelGGL((k_collide<T, true, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, true, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
   else if (emit)
-    hipLaunchKernelGGL((k_collide<T, false, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, false, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
   else
-    hipLaunchKernelGGL((k_collide<T, false, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, false, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
   return hipGetLastError();
 }
 
@@ -882,7 +1034,6 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
   template hipError_t launch_mean_mode<T>(const Consts&, const Bufs&, hipStream_t);                         \
   template hipError_t launch_tridiag<T>(const Consts&, const Bufs&, hipStream_t);                           \
   template hipError_t launch_inverse<T>(const Consts&, const Bufs&, const FftPlan&, hipStream_t);           \
-  template hipError_t launch_collide<T>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);     \
   template hipError_t launch_fields<T>(const Consts&, const Bufs&, double*, double*, double*, double*,       \
                                        double*, hipStream_t);                                               \
   template hipError_t launch_charge_in<T>(const Consts&, const Bufs&, const double*, hipStream_t);          \
@@ -890,5 +1041,8 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
 
 EC_INSTANTIATE(double)
 EC_INSTANTIATE(float)
+template hipError_t launch_collide<double, double>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);
+template hipError_t launch_collide<float, float>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);
+template hipError_t launch_collide<float, double>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);
 
 }  // namespace ec

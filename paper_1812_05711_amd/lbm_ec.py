@@ -14,11 +14,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_ec.so")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, EBUSY = 0, 1, 2, 3, 4, 5
-FP64, FP32_DEV = 0, 1
+FP64, FP32_DEV, FP32_DEV_F64MATH = 0, 1, 2
 INIT_NOISE, INIT_EQ29, INIT_REST = 0, 1, 2
 RATES_ANTISYMMETRIC, RATES_SYMMETRIC = 0, 1
 
-_PRECISION = {"fp64": FP64, "fp32": FP32_DEV, "fp32_dev": FP32_DEV}
+_PRECISION = {"fp64": FP64, "fp32": FP32_DEV, "fp32_dev": FP32_DEV, "fp32_f64math": FP32_DEV_F64MATH}
 _INIT = {"noise": INIT_NOISE, "eq29": INIT_EQ29, "rest": INIT_REST}
 _RATES = {"antisymmetric": RATES_ANTISYMMETRIC, "symmetric": RATES_SYMMETRIC}
 
