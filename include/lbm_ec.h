@@ -175,6 +175,73 @@ int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 /* Releases the handle (host memory only; the caller frees the workspace). */
 void lbm_ec_destroy(lbm_ec_t* h);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent simulations of possibly different sizes and parameters
+ * advanced together: one launch per kernel type covers every live slot, the
+ * step state (current buffer, step count, target) lives on the device, and
+ * each advance is replayed from captured HIP graphs (rebuilt only when the
+ * slot set changes).  Every slot computes exactly what it would compute
+ * alone through lbm_ec_step (same kernels, same arithmetic order).  All
+ * slots of a batch share one precision.  Slots are reusable, so a batch can
+ * serve requests as they arrive (admit while others run, poll, release).
+ *
+ * Device memory: the caller provides one workspace; the batch keeps its
+ * descriptor tables and per-slot diagnostics histories at its start and
+ * places each admitted simulation in the remaining space (first fit). */
+typedef struct lbm_ec_batch lbm_ec_batch_t;
+
+/* Workspace bytes for a batch of max_slots slots with hist_rows history rows
+ * per slot that can hold the n simulations ps[0..n-1] at once (n may be 0 to
+ * get the size of the tables alone).  0 if an argument is invalid. */
+size_t lbm_ec_batch_workspace_bytes(const lbm_ec_params* ps, int32_t n, int32_t max_slots, int32_t hist_rows);
+
+/* Creates an empty batch in the caller's workspace (256-byte aligned).
+ * precision: one of LBM_EC_FP64 / FP32_DEV / FP32_DEV_F64MATH for all slots.
+ * emit_every: every emit_every steps (0 = never) and at its last step each
+ * slot writes its moments and a history row {step, rms u_y, max |u|, sum of
+ * rho_c} (lattice units).  hip_stream: stream for all batch work; NULL makes
+ * the batch create its own (graphs cannot be captured on the null stream).
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int lbm_ec_batch_create(int32_t max_slots, int32_t precision, int32_t emit_every, int32_t hist_rows, void* d_ws,
+                        size_t ws_bytes, void* hip_stream, lbm_ec_batch_t** out);
+
+/* Admits one simulation that will run n_steps steps: finds a free slot and a
+ * free region of the workspace, builds and initialises it (as lbm_ec_create;
+ * waits for the stream) and stores its slot index in *slot.  Returns EBUSY
+ * when no slot or no large enough region is free (nothing changes). */
+int lbm_ec_batch_admit(lbm_ec_batch_t* b, const lbm_ec_params* p, int64_t n_steps, int32_t* slot);
+
+/* Enqueues n steps of the batch: every admitted slot advances by n steps or
+ * until it reaches its n_steps, whichever comes first.  Asynchronous. */
+int lbm_ec_batch_step(lbm_ec_batch_t* b, int64_t n);
+
+/* Waits for the stream and stores in done_slots[0..cap-1] the slots that
+ * have reached their step count since the last poll; *n_done = count. */
+int lbm_ec_batch_poll(lbm_ec_batch_t* b, int32_t* done_slots, int32_t cap, int32_t* n_done);
+
+/* Steps taken by a slot (waits for the stream); -1 for a free slot. */
+int64_t lbm_ec_batch_steps_done(lbm_ec_batch_t* b, int32_t slot);
+
+/* As lbm_ec_fields, for the state at the slot's last emitted step (its final
+ * step once it is done).  Asynchronous. */
+int lbm_ec_batch_fields(lbm_ec_batch_t* b, int32_t slot, double* rho, double* ux, double* uy, double* rho_c,
+                        double* phi);
+
+/* Copies the first `rows` history rows of a slot (4 doubles each, host
+ * memory); waits for the stream.  Row r holds step (r+1) * emit_every, the
+ * last row the final step when that is not a multiple of emit_every; unused
+ * rows are zero. */
+int lbm_ec_batch_history(lbm_ec_batch_t* b, int32_t slot, double* out, int32_t rows);
+
+/* Frees a slot and its workspace region (waits for the stream). */
+int lbm_ec_batch_release(lbm_ec_batch_t* b, int32_t slot);
+
+/* Largest free contiguous region of the batch workspace, bytes. */
+size_t lbm_ec_batch_free_bytes(lbm_ec_batch_t* b);
+
+/* Releases the batch (waits for its stream; the caller frees the workspace). */
+void lbm_ec_batch_destroy(lbm_ec_batch_t* b);
+
 /* Message of the last error on this thread ("" if none). */
 const char* lbm_ec_last_error(void);
 

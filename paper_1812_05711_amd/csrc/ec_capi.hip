@@ -389,9 +389,411 @@ int run_steps(lbm_ec* h, int64_t n) {
   return LBM_EC_OK;
 }
 
+// Builds an instance in the device region ws (L.total bytes) on stream s and
+// enqueues its initial state; waits for the stream.
+int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStream_t s) {
+  const Layout L = make_layout(*p);
+  h->p = *p;
+  h->L = L;
+  h->s = s;
+  h->fp32 = p->precision != LBM_EC_FP64;
+  h->plan = make_plan(p->nx);
+  h->b.f[0] = ws + L.off_f[0];
+  h->b.f[1] = ws + L.off_f[1];
+  h->b.g[0] = ws + L.off_g[0];
+  h->b.g[1] = ws + L.off_g[1];
+  h->b.phi = ws + L.off_phi;
+  h->b.spec = ws + L.off_spec;
+  h->b.tt = ws + L.off_tt;
+  h->b.ends = ws + L.off_ends;
+  h->b.gh = ws + L.off_gh;
+  h->b.iface = ws + L.off_iface;
+  h->b.tw = ws + L.off_tw;
+  h->b.rows = ws + L.off_rows;
+  h->b.rowsd = (double*)(ws + L.off_rowsd);
+  h->b.dmean = (double*)(ws + L.off_dmean);
+  h->b.mom = (double*)(ws + L.off_mom);
+  h->b.stats = (double*)(ws + L.off_stats);
+  int rc = h->fp32 ? setup<float>(h, ws) : setup<double>(h, ws);
+  if (!rc) {
+    if (p->precision == LBM_EC_FP64)
+      rc = init_state<double, double>(h);
+    else if (p->precision == LBM_EC_FP32_DEV)
+      rc = init_state<float, float>(h);
+    else
+      rc = init_state<float, double>(h);
+  }
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(h->s);
+    if (e != hipSuccess) rc = fail(LBM_EC_EHIP, std::string("initial state: ") + hipGetErrorString(e));
+  }
+  return rc;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+constexpr int kGraphSteps = 16;  // steps per captured graph
+
+struct Slot {
+  bool used = false;
+  bool reported = false;
+  lbm_ec inst;
+  size_t off = 0, bytes = 0;  // region in the batch workspace
+  int64_t target = 0;
+  int hist_cap = 0;
+  double* hist = nullptr;
+};
+
+struct Range {
+  size_t off, bytes;
+};
+
+}  // namespace
+
+struct lbm_ec_batch {
+  int max_slots;
+  int precision;
+  int emit_every;
+  unsigned char* ws;
+  size_t ws_bytes;
+  hipStream_t s;
+  bool own_stream;
+  std::vector<Slot> slots;
+  std::vector<Range> free_list;  // sorted by offset
+  // device tables at the start of the workspace
+  ec::SlotDesc* d_desc;
+  int* d_off;
+  double* d_hist;
+  int hist_rows;  // history rows per slot
+  size_t heap_off;
+  // current launch tables
+  std::vector<int> order;  // slot index of each descriptor entry
+  int totals[ec::BK_COUNT];
+  size_t lds;
+  bool dirty;
+  hipGraphExec_t g_many, g_one;
+  bool have_graphs;
+};
+
+namespace {
+
+size_t batch_header_bytes(int max_slots, int hist_rows) {
+  size_t o = align_up(sizeof(ec::SlotDesc) * (size_t)max_slots);
+  o += align_up(sizeof(int) * (size_t)ec::BK_COUNT * (max_slots + 1));
+  o += align_up(sizeof(double) * 4 * (size_t)hist_rows * max_slots);
+  return o;
+}
+
+bool heap_alloc(lbm_ec_batch* B, size_t bytes, size_t* off) {
+  bytes = align_up(bytes);
+  for (size_t i = 0; i < B->free_list.size(); ++i) {
+    Range& r = B->free_list[i];
+    if (r.bytes >= bytes) {
+      *off = r.off;
+      r.off += bytes;
+      r.bytes -= bytes;
+      if (r.bytes == 0) B->free_list.erase(B->free_list.begin() + i);
+      return true;
+    }
+  }
+  return false;
+}
+
+void heap_free(lbm_ec_batch* B, size_t off, size_t bytes) {
+  bytes = align_up(bytes);
+  std::vector<Range>& F = B->free_list;
+  size_t i = 0;
+  while (i < F.size() && F[i].off < off) ++i;
+  F.insert(F.begin() + i, Range{off, bytes});
+  // coalesce with the neighbours
+  if (i + 1 < F.size() && F[i].off + F[i].bytes == F[i + 1].off) {
+    F[i].bytes += F[i + 1].bytes;
+    F.erase(F.begin() + i + 1);
+  }
+  if (i > 0 && F[i - 1].off + F[i - 1].bytes == F[i].off) {
+    F[i - 1].bytes += F[i].bytes;
+    F.erase(F.begin() + i);
+  }
+}
+
+void drop_graphs(lbm_ec_batch* B) {
+  if (B->have_graphs) {
+    (void)hipGraphExecDestroy(B->g_many);
+    (void)hipGraphExecDestroy(B->g_one);
+    B->have_graphs = false;
+  }
+}
+
+template <typename T, typename C>
+int capture(lbm_ec_batch* B, int steps, hipGraphExec_t* out) {
+  hipGraph_t g;
+  EC_HIP(hipStreamBeginCapture(B->s, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < steps && le == hipSuccess; ++k)
+    le = ec::launch_batch_step<T, C>(B->d_desc, B->d_off, B->totals, (int)B->order.size(), B->lds, B->s);
+  hipError_t ee = hipStreamEndCapture(B->s, &g);
+  if (le != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture launch: ") + hipGetErrorString(le));
+  if (ee != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture: ") + hipGetErrorString(ee));
+  hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch graph: ") + hipGetErrorString(ie));
+  return LBM_EC_OK;
+}
+
+// Reads the device step state back into the slots.
+int pull_state(lbm_ec_batch* B) {
+  const int ns = (int)B->order.size();
+  if (ns == 0) return LBM_EC_OK;
+  std::vector<ec::SlotDesc> D(ns);
+  EC_HIP(hipMemcpyAsync(D.data(), B->d_desc, sizeof(ec::SlotDesc) * ns, hipMemcpyDeviceToHost, B->s));
+  EC_HIP(hipStreamSynchronize(B->s));
+  for (int q = 0; q < ns; ++q) {
+    Slot& sl = B->slots[B->order[q]];
+    sl.inst.cur = D[q].cur;
+    sl.inst.steps = D[q].steps_done;
+  }
+  return LBM_EC_OK;
+}
+
+// New descriptor and offset tables for the slots with steps left, and their graphs.
+int rebuild(lbm_ec_batch* B) {
+  int rc = pull_state(B);
+  if (rc) return rc;
+  drop_graphs(B);
+  B->order.clear();
+  for (int i = 0; i < B->max_slots; ++i) {
+    const Slot& sl = B->slots[i];
+    if (sl.used && sl.inst.steps < sl.target) B->order.push_back(i);
+  }
+  const int ns = (int)B->order.size();
+  std::vector<ec::SlotDesc> D(ns);
+  std::vector<int> off((size_t)ec::BK_COUNT * (ns + 1), 0);
+  B->lds = 0;
+  for (int k = 0; k < ec::BK_COUNT; ++k) B->totals[k] = 0;
+  for (int q = 0; q < ns; ++q) {
+    Slot& sl = B->slots[B->order[q]];
+    ec::SlotDesc& d = D[q];
+    d.c = sl.inst.c;
+    d.b = sl.inst.b;
+    d.plan = sl.inst.plan;
+    d.cur = sl.inst.cur;
+    d.active = 1;
+    d.emit_every = B->emit_every;
+    d.hist_cap = sl.hist_cap;
+    d.steps_done = sl.inst.steps;
+    d.steps_target = sl.target;
+    d.hist = sl.hist;
+    const size_t lds = sl.inst.fp32 ? ec::fft_lds_bytes<float>(sl.inst.p.nx) : ec::fft_lds_bytes<double>(sl.inst.p.nx);
+    B->lds = std::max(B->lds, lds);
+    for (int k = 0; k < ec::BK_COUNT; ++k) {
+      off[(size_t)k * (ns + 1) + q] = B->totals[k];
+      B->totals[k] += ec::batch_blocks(d.c, k);
+    }
+  }
+  for (int k = 0; k < ec::BK_COUNT; ++k) off[(size_t)k * (ns + 1) + ns] = B->totals[k];
+  if (ns) {
+    EC_HIP(hipMemcpyAsync(B->d_desc, D.data(), sizeof(ec::SlotDesc) * ns, hipMemcpyHostToDevice, B->s));
+    EC_HIP(hipMemcpyAsync(B->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, B->s));
+    EC_HIP(hipStreamSynchronize(B->s));
+    if (B->precision == LBM_EC_FP64) {
+      if ((rc = capture<double, double>(B, kGraphSteps, &B->g_many))) return rc;
+      if ((rc = capture<double, double>(B, 1, &B->g_one))) return rc;
+    } else if (B->precision == LBM_EC_FP32_DEV) {
+      if ((rc = capture<float, float>(B, kGraphSteps, &B->g_many))) return rc;
+      if ((rc = capture<float, float>(B, 1, &B->g_one))) return rc;
+    } else {
+      if ((rc = capture<float, double>(B, kGraphSteps, &B->g_many))) return rc;
+      if ((rc = capture<float, double>(B, 1, &B->g_one))) return rc;
+    }
+    B->have_graphs = true;
+  }
+  B->dirty = false;
+  return LBM_EC_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t lbm_ec_batch_workspace_bytes(const lbm_ec_params* ps, int32_t n, int32_t max_slots, int32_t hist_rows) {
+  if (max_slots < 1 || hist_rows < 1 || n < 0 || (n > 0 && !ps)) return 0;
+  size_t total = batch_header_bytes(max_slots, hist_rows);
+  for (int i = 0; i < n; ++i) {
+    if (validate(&ps[i]) != LBM_EC_OK) return 0;
+    total += align_up(make_layout(ps[i]).total);
+  }
+  return total;
+}
+
+int lbm_ec_batch_create(int32_t max_slots, int32_t precision, int32_t emit_every, int32_t hist_rows, void* d_ws,
+                        size_t ws_bytes, void* hip_stream, lbm_ec_batch_t** out) {
+  g_err.clear();
+  if (!out) return fail(LBM_EC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 4096) return fail(LBM_EC_EINVAL, "max_slots must be in 1..4096");
+  if (precision != LBM_EC_FP64 && precision != LBM_EC_FP32_DEV && precision != LBM_EC_FP32_DEV_F64MATH)
+    return fail(LBM_EC_EINVAL, "unknown precision");
+  if (emit_every < 0 || hist_rows < 1) return fail(LBM_EC_EINVAL, "emit_every >= 0 and hist_rows >= 1 required");
+  if (!d_ws) return fail(LBM_EC_EINVAL, "workspace is NULL");
+  if (((uintptr_t)d_ws) % kAlign) return fail(LBM_EC_ENOMEM, "workspace must be 256-byte aligned");
+  const size_t head = batch_header_bytes(max_slots, hist_rows);
+  if (ws_bytes < head) return fail(LBM_EC_ENOMEM, "workspace smaller than the batch tables");
+  lbm_ec_batch* B = new lbm_ec_batch();
+  B->max_slots = max_slots;
+  B->precision = precision;
+  B->emit_every = emit_every;
+  B->ws = (unsigned char*)d_ws;
+  B->ws_bytes = ws_bytes;
+  B->own_stream = hip_stream == nullptr;
+  if (B->own_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete B;
+      return fail(LBM_EC_EHIP, std::string("stream: ") + hipGetErrorString(e));
+    }
+  } else {
+    B->s = (hipStream_t)hip_stream;
+  }
+  B->slots.resize(max_slots);
+  size_t o = 0;
+  B->d_desc = (ec::SlotDesc*)(B->ws + o);
+  o += align_up(sizeof(ec::SlotDesc) * (size_t)max_slots);
+  B->d_off = (int*)(B->ws + o);
+  o += align_up(sizeof(int) * (size_t)ec::BK_COUNT * (max_slots + 1));
+  B->d_hist = (double*)(B->ws + o);
+  B->hist_rows = hist_rows;
+  o += align_up(sizeof(double) * 4 * (size_t)hist_rows * max_slots);
+  B->heap_off = o;
+  B->free_list.push_back(Range{o, ws_bytes - o});
+  B->dirty = true;
+  B->have_graphs = false;
+  *out = B;
+  return LBM_EC_OK;
+}
+
+int lbm_ec_batch_admit(lbm_ec_batch_t* B, const lbm_ec_params* p, int64_t n_steps, int32_t* slot) {
+  if (!B || !p || !slot) return fail(LBM_EC_EINVAL, "NULL argument");
+  int rc = validate(p);
+  if (rc) return rc;
+  if (p->precision != B->precision) return fail(LBM_EC_EINVAL, "precision differs from the batch's");
+  if (n_steps < 1) return fail(LBM_EC_EINVAL, "n_steps must be positive");
+  int idx = -1;
+  for (int i = 0; i < B->max_slots; ++i)
+    if (!B->slots[i].used) {
+      idx = i;
+      break;
+    }
+  if (idx < 0) return fail(LBM_EC_EBUSY, "no free slot");
+  const Layout L = make_layout(*p);
+  size_t off;
+  if (!heap_alloc(B, L.total, &off)) return fail(LBM_EC_EBUSY, "not enough free workspace for this instance");
+  // the step state of the running slots is on the device: read it before the
+  // slot set changes
+  if ((rc = pull_state(B))) {
+    heap_free(B, off, L.total);
+    return rc;
+  }
+  Slot& sl = B->slots[idx];
+  sl = Slot();
+  if ((rc = build_instance(&sl.inst, p, B->ws + off, B->s))) {
+    heap_free(B, off, L.total);
+    return rc;
+  }
+  sl.used = true;
+  sl.off = off;
+  sl.bytes = L.total;
+  sl.target = n_steps;
+  sl.hist = B->d_hist + 4 * (size_t)B->hist_rows * idx;
+  sl.hist_cap = B->hist_rows;
+  EC_HIP(hipMemsetAsync(sl.hist, 0, sizeof(double) * 4 * B->hist_rows, B->s));
+  B->dirty = true;
+  *slot = idx;
+  return LBM_EC_OK;
+}
+
+int lbm_ec_batch_step(lbm_ec_batch_t* B, int64_t n) {
+  if (!B) return fail(LBM_EC_EINVAL, "NULL argument");
+  if (n < 0) return fail(LBM_EC_EINVAL, "negative step count");
+  int rc;
+  if (B->dirty && (rc = rebuild(B))) return rc;
+  if (B->order.empty()) return LBM_EC_OK;
+  for (int64_t k = 0; k + kGraphSteps <= n; k += kGraphSteps) EC_HIP(hipGraphLaunch(B->g_many, B->s));
+  for (int64_t k = 0; k < n % kGraphSteps; ++k) EC_HIP(hipGraphLaunch(B->g_one, B->s));
+  return LBM_EC_OK;
+}
+
+int lbm_ec_batch_poll(lbm_ec_batch_t* B, int32_t* done_slots, int32_t cap, int32_t* n_done) {
+  if (!B || !n_done || (cap > 0 && !done_slots)) return fail(LBM_EC_EINVAL, "NULL argument");
+  int rc = pull_state(B);
+  if (rc) return rc;
+  int n = 0;
+  for (int i = 0; i < B->max_slots; ++i) {
+    Slot& sl = B->slots[i];
+    if (sl.used && !sl.reported && sl.inst.steps >= sl.target && n < cap) {
+      done_slots[n++] = i;
+      sl.reported = true;
+      B->dirty = true;  // drop the finished slot from the launch tables
+    }
+  }
+  *n_done = n;
+  return LBM_EC_OK;
+}
+
+int64_t lbm_ec_batch_steps_done(lbm_ec_batch_t* B, int32_t slot) {
+  if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return -1;
+  if (pull_state(B)) return -1;
+  return B->slots[slot].inst.steps;
+}
+
+int lbm_ec_batch_fields(lbm_ec_batch_t* B, int32_t slot, double* rho, double* ux, double* uy, double* rho_c,
+                        double* phi) {
+  if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
+  lbm_ec* h = &B->slots[slot].inst;
+  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, rho, ux, uy, rho_c, phi, B->s)
+                 : ec::launch_fields<double>(h->c, h->b, rho, ux, uy, rho_c, phi, B->s));
+  return LBM_EC_OK;
+}
+
+int lbm_ec_batch_history(lbm_ec_batch_t* B, int32_t slot, double* out, int32_t rows) {
+  if (!B || !out || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
+  const int r = std::min(rows, B->hist_rows);
+  EC_HIP(hipMemcpyAsync(out, B->slots[slot].hist, sizeof(double) * 4 * r, hipMemcpyDeviceToHost, B->s));
+  EC_HIP(hipStreamSynchronize(B->s));
+  return LBM_EC_OK;
+}
+
+int lbm_ec_batch_release(lbm_ec_batch_t* B, int32_t slot) {
+  if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
+  int rc = pull_state(B);
+  if (rc) return rc;
+  EC_HIP(hipStreamSynchronize(B->s));
+  Slot& sl = B->slots[slot];
+  for (hipEvent_t e : sl.inst.prof.ev) (void)hipEventDestroy(e);
+  heap_free(B, sl.off, sl.bytes);
+  sl = Slot();
+  B->dirty = true;
+  return LBM_EC_OK;
+}
+
+size_t lbm_ec_batch_free_bytes(lbm_ec_batch_t* B) {
+  if (!B) return 0;
+  size_t best = 0;
+  for (const Range& r : B->free_list) best = std::max(best, r.bytes);
+  return best;
+}
+
+void lbm_ec_batch_destroy(lbm_ec_batch_t* B) {
+  if (!B) return;
+  (void)hipStreamSynchronize(B->s);
+  drop_graphs(B);
+  for (Slot& sl : B->slots)
+    for (hipEvent_t e : sl.inst.prof.ev) (void)hipEventDestroy(e);
+  if (B->own_stream) (void)hipStreamDestroy(B->s);
+  delete B;
+}
 
 int lbm_ec_params_default(lbm_ec_params* p) {
   if (!p) return fail(LBM_EC_EINVAL, "params is NULL");

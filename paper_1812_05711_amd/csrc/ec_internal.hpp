@@ -96,6 +96,34 @@ struct Bufs {
   double* stats; // [16]
 };
 
+// One slot of a batch: an instance's constants, buffers and transform plan,
+// and its step state, which the device advances so that a captured
+// multi-step graph needs no host updates between steps.
+struct SlotDesc {
+  Consts c;
+  Bufs b;
+  FftPlan plan;
+  int cur;             // buffer holding the latest post-collision populations
+  int active;          // 1 while steps_done < steps_target
+  int emit_every;      // moments and diagnostics every emit_every steps and at the end
+  int hist_cap;        // rows of the diagnostics history
+  long long steps_done, steps_target;
+  double* hist;        // [hist_cap][4]: step, rms u_y, max |u|, sum of rho_c (lattice units)
+};
+
+// Batched kernels; slot s owns the blocks [off[k][s], off[k][s+1]) of launch k.
+enum BatchKernel { BK_FORWARD = 0, BK_MEAN, BK_TRI_LOCAL, BK_TRI_REDUCED, BK_INVERSE, BK_COLLIDE, BK_STATS, BK_COUNT };
+
+// Blocks that kernel k uses for one instance.
+int batch_blocks(const Consts& c, int k);
+
+// Enqueues one batched step (all kernels, then the device-side advance) for
+// ns slots.  d_off holds BK_COUNT rows of ns + 1 offsets; totals[k] is the
+// block count of launch k; lds the dynamic LDS of the transforms.
+template <typename T, typename C>
+hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
+                             hipStream_t s);
+
 // Kernel launchers (ec_kernels.hip).  All enqueue on `s` and return the
 // launch status.
 template <typename T>

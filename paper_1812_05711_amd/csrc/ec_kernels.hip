@@ -317,15 +317,15 @@ __device__ __forceinline__ void local_pop(const Consts& c, const T* __restrict__
 // s_m = -DFT(rho_c - r)_m / eps for m = 1 .. nx/2 (Eq. 4, 19) and the FP64
 // row sums of the charge deviation (the m = 0 mode).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
-                                                 const double* __restrict__ drc_field, FftPlan pl,
-                                                 const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
-                                                 double* __restrict__ dcsum) {
+__device__ __forceinline__ void forward_body(const Consts& c, const T* __restrict__ G, const T* __restrict__ rows,
+                                             const double* __restrict__ drc_field, const FftPlan& pl,
+                                             const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
+                                             double* __restrict__ dcsum, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* a = reinterpret_cast<C2<T>*>(smem);
   C2<T>* b = a + pl.n;
   double* red = reinterpret_cast<double*>(b);  // idle until the transform
-  const int j0 = 2 * blockIdx.x, j1 = j0 + 1;
+  const int j0 = 2 * bx, j1 = j0 + 1;
   const bool has1 = j1 < c.ny;
   double s0 = 0.0, s1 = 0.0;
   for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
@@ -370,6 +370,14 @@ __global__ void __launch_bounds__(256) k_forward(Consts c, const T* __restrict__
   }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
+                                                 const double* __restrict__ drc_field, FftPlan pl,
+                                                 const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
+                                                 double* __restrict__ dcsum) {
+  forward_body<T, MODE>(c, G, rows, drc_field, pl, tw, spec, dcsum, blockIdx.x);
+}
+
 // --------------------------------------------------- x-mean mode (m = 0)
 // The x-mean potential by integrating Gauss's law twice (flux form of the
 // m = 0 row of Eq. 18 / 24 with the electrode ghost rows):
@@ -378,8 +386,8 @@ __global__ void __launch_bounds__(256) k_forward(Consts c, const T* __restrict__
 //   D(-1) = (phi_upper - phi_lower)/ny - (S(ny-1) + 2 sum_{k<ny-1} S(k)) / (2 ny)
 //   phi_mean(j) = phi_lower + D(-1)/2 + sum_{k<j} D(k),  E_y mean = -(D(j) + D(j-1))/2
 // One block; FP64 throughout.
-__global__ void __launch_bounds__(1024) k_mean_mode(Consts c, double* __restrict__ rowsd,
-                                                     double* __restrict__ dmean) {
+__device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restrict__ rowsd,
+                                               double* __restrict__ dmean) {
   __shared__ double part[1024];
   __shared__ double red[32];
   const int ny = c.ny;
@@ -450,6 +458,11 @@ __global__ void __launch_bounds__(1024) k_mean_mode(Consts c, double* __restrict
   }
 }
 
+__global__ void __launch_bounds__(1024) k_mean_mode(Consts c, double* __restrict__ rowsd,
+                                                     double* __restrict__ dmean) {
+  mean_mode_body(c, rowsd, dmean);
+}
+
 // ------------------------------------------------- per-wavenumber solves
 // m = 1 .. nx/2: phi(j+1) - (2 + kappa_m^2) phi(j) + phi(j-1) = s(j) with
 // homogeneous ghost closures (Eq. 20, 24-25 as a tridiagonal per m), solved
@@ -473,10 +486,10 @@ __device__ __forceinline__ T ttab(const T* __restrict__ tt, int MP, int type, in
 // chunk's own system in registers; y overwrites the spectrum, its first and
 // last rows go to `ends`.
 template <typename T>
-__global__ void __launch_bounds__(64) k_tri_local(Consts c, const T* __restrict__ tt, C2<T>* __restrict__ spec,
-                                                  C2<T>* __restrict__ ends) {
-  const int m = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
+__device__ __forceinline__ void tri_local_body(const Consts& c, const T* __restrict__ tt, C2<T>* __restrict__ spec,
+                                               C2<T>* __restrict__ ends, int bx, int by) {
+  const int m = 1 + bx * blockDim.x + threadIdx.x;
+  const int k = by;
   if (m >= c.M) return;
   const int s0 = k * kChunk;
   const int len = min(kChunk, c.ny - s0);
@@ -512,6 +525,12 @@ __global__ void __launch_bounds__(64) k_tri_local(Consts c, const T* __restrict_
   ends[(2 * (size_t)k + 1) * MP + m] = last;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(64) k_tri_local(Consts c, const T* __restrict__ tt, C2<T>* __restrict__ spec,
+                                                  C2<T>* __restrict__ ends) {
+  tri_local_body<T>(c, tt, spec, ends, blockIdx.x, blockIdx.y);
+}
+
 // One thread per m: the interface system.  Interface k (between chunks k
 // and k+1) carries a_k = x(last row of chunk k) and b_k = x(first row of
 // chunk k+1):
@@ -520,9 +539,10 @@ __global__ void __launch_bounds__(64) k_tri_local(Consts c, const T* __restrict_
 // (v_s, v_e, w_s, w_e: first / last entries of the chunk responses), solved
 // by block elimination with 2x2 pivots [[1, beta], [gamma, 1]].
 template <typename T>
-__global__ void __launch_bounds__(64) k_tri_reduced(Consts c, const T* __restrict__ tt, const C2<T>* __restrict__ ends,
-                                                    T* __restrict__ gh, C2<T>* __restrict__ iface) {
-  const int m = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void tri_reduced_body(const Consts& c, const T* __restrict__ tt,
+                                                 const C2<T>* __restrict__ ends, T* __restrict__ gh,
+                                                 C2<T>* __restrict__ iface, int bx) {
+  const int m = 1 + bx * blockDim.x + threadIdx.x;
   if (m >= c.M) return;
   const int nc = c.NC;
   if (nc < 2) return;
@@ -571,6 +591,12 @@ __global__ void __launch_bounds__(64) k_tri_reduced(Consts c, const T* __restric
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(64) k_tri_reduced(Consts c, const T* __restrict__ tt, const C2<T>* __restrict__ ends,
+                                                    T* __restrict__ gh, C2<T>* __restrict__ iface) {
+  tri_reduced_body<T>(c, tt, ends, gh, iface, blockIdx.x);
+}
+
 // Solution of row j, wavenumber m: the chunk-local y (in spec) plus the
 // responses to the interface values.
 template <typename T>
@@ -602,13 +628,14 @@ __device__ __forceinline__ C2<T> solved_mode(const Consts& c, const C2<T>* __res
 // two solved spectra (m = 0 left out: it lives in the x-mean row), inverse
 // transform, 1/nx, real / imaginary parts to the two rows of phi.
 template <typename T>
-__global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
-                                                 const C2<T>* __restrict__ iface, FftPlan pl,
-                                                 const C2<T>* __restrict__ tw, T* __restrict__ phi) {
+__device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __restrict__ spec,
+                                             const T* __restrict__ tt, const C2<T>* __restrict__ iface,
+                                             const FftPlan& pl, const C2<T>* __restrict__ tw, T* __restrict__ phi,
+                                             int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* a = reinterpret_cast<C2<T>*>(smem);
   C2<T>* b = a + pl.n;
-  const int j0 = 2 * blockIdx.x, j1 = j0 + 1;
+  const int j0 = 2 * bx, j1 = j0 + 1;
   const bool has1 = j1 < c.ny;
   const int N = pl.n;
   for (int m = threadIdx.x; m < N; m += blockDim.x) {
@@ -635,6 +662,13 @@ __global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restri
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
+                                                 const C2<T>* __restrict__ iface, FftPlan pl,
+                                                 const C2<T>* __restrict__ tw, T* __restrict__ phi) {
+  inverse_body<T>(c, spec, tt, iface, pl, tw, phi, blockIdx.x);
+}
+
 // ------------------------------------------- fused collide (and stream)
 // One thread per node.  PULL: gathers the pre-collision populations from the
 // post-collision arrays with the wall rules (the streaming of Eq. 8-9);
@@ -642,13 +676,15 @@ __global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restri
 // Then the moments (Eq. 5-7), E = -grad phi (central differences, the mean
 // row in FP64), the equilibria (Eq. 10-11), the source (Eq. 12) and the TRT
 // collisions (Eq. 8-9, 13-15); writes the post-collision deviations.
-template <typename T, typename C, bool PULL, bool EMIT>
-__global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__ Fin, const T* __restrict__ Gin,
-                                                 T* __restrict__ Fout, T* __restrict__ Gout,
-                                                 const T* __restrict__ phi, const T* __restrict__ rows,
-                                                 const double* __restrict__ rowsd, double* __restrict__ mom) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+// mom == nullptr: no moments are emitted.
+template <typename T, typename C, bool PULL>
+__device__ __forceinline__ void collide_body(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
+                                             T* __restrict__ Fout, T* __restrict__ Gout,
+                                             const T* __restrict__ phi, const T* __restrict__ rows,
+                                             const double* __restrict__ rowsd, double* __restrict__ mom, int bx,
+                                             int by) {
+  const int x = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
   if (x >= c.nx || j >= c.ny) return;
   C f[9], g[9];
   {
@@ -693,7 +729,7 @@ __global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__
   const C uy = (jy + C(0.5) * dfy) / rho;
   const C vx = ux + C(c.K) * ex;
   const C vy = uy + C(c.K) * ey;
-  if (EMIT) {
+  if (mom != nullptr) {
     const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
     mom[k] = (double)drho;
     mom[n + k] = (double)ux;
@@ -757,6 +793,14 @@ __global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__
     Fout[i * plane + idx] = (T)fo[i];
     Gout[i * plane + idx] = (T)go[i];
   }
+}
+
+template <typename T, typename C, bool PULL, bool EMIT>
+__global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__ Fin, const T* __restrict__ Gin,
+                                                 T* __restrict__ Fout, T* __restrict__ Gout,
+                                                 const T* __restrict__ phi, const T* __restrict__ rows,
+                                                 const double* __restrict__ rowsd, double* __restrict__ mom) {
+  collide_body<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------ init kernels
@@ -917,6 +961,180 @@ __global__ void __launch_bounds__(1024) k_stats(Consts c, const double* __restri
     out[7] = me[0];
   }
 }
+
+// ------------------------------------------------------ batched kernels
+// One launch per kernel type covers every slot of a batch; each block finds
+// its slot from the per-launch block offsets.
+
+__device__ __forceinline__ int find_slot(const int* __restrict__ off, int ns, int b) {
+  int lo = 0, hi = ns;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool slot_emits(const SlotDesc& d) {
+  const long long k = d.steps_done + 1;  // the step being taken
+  return k == d.steps_target || (d.emit_every > 0 && k % d.emit_every == 0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_forward(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+  const int s = find_slot(off, ns, blockIdx.x);
+  const SlotDesc& d = D[s];
+  if (!d.active) return;
+  forward_body<T, 0>(d.c, (const T*)d.b.g[d.cur], (const T*)d.b.rows, nullptr, d.plan, (const C2<T>*)d.b.tw,
+                     (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny, blockIdx.x - off[s]);
+}
+
+__global__ void __launch_bounds__(1024) kb_mean_mode(const SlotDesc* __restrict__ D, const int* __restrict__ off,
+                                                     int ns) {
+  const int s = find_slot(off, ns, blockIdx.x);
+  const SlotDesc& d = D[s];
+  if (!d.active) return;
+  mean_mode_body(d.c, d.b.rowsd, d.b.dmean);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) kb_tri_local(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+  const int s = find_slot(off, ns, blockIdx.x);
+  const SlotDesc& d = D[s];
+  if (!d.active) return;
+  const int lb = blockIdx.x - off[s];
+  const int nbx = (d.c.M - 1 + 63) / 64;
+  tri_local_body<T>(d.c, (const T*)d.b.tt, (C2<T>*)d.b.spec, (C2<T>*)d.b.ends, lb % nbx, lb / nbx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) kb_tri_reduced(const SlotDesc* __restrict__ D, const int* __restrict__ off,
+                                                     int ns) {
+  const int s = find_slot(off, ns, blockIdx.x);
+  const SlotDesc& d = D[s];
+  if (!d.active) return;
+  tri_reduced_body<T>(d.c, (const T*)d.b.tt, (const C2<T>*)d.b.ends, (T*)d.b.gh, (C2<T>*)d.b.iface,
+                      blockIdx.x - off[s]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_inverse(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+  const int s = find_slot(off, ns, blockIdx.x);
+  const SlotDesc& d = D[s];
+  if (!d.active) return;
+  inverse_body<T>(d.c, (const C2<T>*)d.b.spec, (const T*)d.b.tt, (const C2<T>*)d.b.iface, d.plan,
+                  (const C2<T>*)d.b.tw, (T*)d.b.phi, blockIdx.x - off[s]);
+}
+
+template <typename T, typename C>
+__global__ void __launch_bounds__(256) kb_collide(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+  const int s = find_slot(off, ns, blockIdx.x);
+  const SlotDesc& d = D[s];
+  if (!d.active) return;
+  const int lb = blockIdx.x - off[s];
+  const int nbx = (d.c.nx + 63) / 64;
+  const int src = d.cur, dst = 1 - d.cur;
+  collide_body<T, C, true>(d.c, (const T*)d.b.f[src], (const T*)d.b.g[src], (T*)d.b.f[dst], (T*)d.b.g[dst],
+                           (const T*)d.b.phi, (const T*)d.b.rows, d.b.rowsd, slot_emits(d) ? d.b.mom : nullptr,
+                           lb % nbx, lb / nbx);
+}
+
+// Diagnostics of the slots that emitted moments this step (one block each):
+// rms u_y, max |u| and the total charge, into the slot's history.
+__global__ void __launch_bounds__(256) kb_stats(SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+  __shared__ double red[32];
+  __shared__ double mx[256];
+  const int s = find_slot(off, ns, blockIdx.x);
+  const SlotDesc& d = D[s];
+  if (!d.active || !slot_emits(d) || d.hist == nullptr) return;
+  const long long k = d.steps_done + 1;
+  const int row = (d.emit_every > 0 && k % d.emit_every == 0) ? (int)(k / d.emit_every) - 1 : d.hist_cap - 1;
+  if (row < 0 || row >= d.hist_cap) return;
+  const size_t n = (size_t)d.c.ny * d.c.nx;
+  double suy = 0, srho_c = 0, mu = 0;
+  for (size_t q = threadIdx.x; q < n; q += blockDim.x) {
+    const int j = (int)(q / d.c.nx);
+    const double ux = d.b.mom[n + q], uy = d.b.mom[2 * n + q];
+    suy += uy * uy;
+    mu = fmax(mu, sqrt(ux * ux + uy * uy));
+    srho_c += d.b.rowsd[ROWD_R * d.c.ny + j] + d.b.mom[3 * n + q];
+  }
+  suy = block_sum(suy, red);
+  __syncthreads();
+  srho_c = block_sum(srho_c, red);
+  mx[threadIdx.x] = mu;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* h = d.hist + 4 * (size_t)row;
+    h[0] = (double)k;
+    h[1] = sqrt(suy / (double)n);
+    h[2] = mx[0];
+    h[3] = srho_c;
+  }
+}
+
+// Device-side end of a batched step: flip the buffers of the active slots,
+// count the step, retire slots that reached their target.
+__global__ void kb_advance(SlotDesc* __restrict__ D, int ns) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  SlotDesc& d = D[s];
+  if (!d.active) return;
+  d.cur = 1 - d.cur;
+  d.steps_done += 1;
+  if (d.steps_done >= d.steps_target) d.active = 0;
+}
+
+int batch_blocks(const Consts& c, int k) {
+  const int nm = c.M - 1;
+  switch (k) {
+    case BK_FORWARD:
+    case BK_INVERSE: return (c.ny + 1) / 2;
+    case BK_MEAN: return 1;
+    case BK_TRI_LOCAL: return nm > 0 ? ((nm + 63) / 64) * c.NC : 0;
+    case BK_TRI_REDUCED: return (nm > 0 && c.NC >= 2) ? (nm + 63) / 64 : 0;
+    case BK_COLLIDE: return ((c.nx + 63) / 64) * ((c.ny + 3) / 4);
+    case BK_STATS: return 1;
+  }
+  return 0;
+}
+
+template <typename T, typename C>
+hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
+                             hipStream_t s) {
+  const int row = ns + 1;
+  SlotDesc* D = const_cast<SlotDesc*>(d_desc);
+  if (totals[BK_FORWARD])
+    hipLaunchKernelGGL(kb_forward<T>, dim3(totals[BK_FORWARD]), dim3(256), lds, s, d_desc, d_off + BK_FORWARD * row, ns);
+  if (totals[BK_MEAN])
+    hipLaunchKernelGGL(kb_mean_mode, dim3(totals[BK_MEAN]), dim3(1024), 0, s, d_desc, d_off + BK_MEAN * row, ns);
+  if (totals[BK_TRI_LOCAL])
+    hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(64), 0, s, d_desc,
+                       d_off + BK_TRI_LOCAL * row, ns);
+  if (totals[BK_TRI_REDUCED])
+    hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(64), 0, s, d_desc,
+                       d_off + BK_TRI_REDUCED * row, ns);
+  if (totals[BK_INVERSE])
+    hipLaunchKernelGGL(kb_inverse<T>, dim3(totals[BK_INVERSE]), dim3(256), lds, s, d_desc, d_off + BK_INVERSE * row, ns);
+  if (totals[BK_COLLIDE])
+    hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(64, 4), 0, s, d_desc,
+                       d_off + BK_COLLIDE * row, ns);
+  if (totals[BK_STATS])
+    hipLaunchKernelGGL(kb_stats, dim3(totals[BK_STATS]), dim3(256), 0, s, D, d_off + BK_STATS * row, ns);
+  hipLaunchKernelGGL(kb_advance, dim3((ns + 63) / 64), dim3(64), 0, s, D, ns);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_step<double, double>(const SlotDesc*, const int*, const int*, int, size_t, hipStream_t);
+template hipError_t launch_batch_step<float, float>(const SlotDesc*, const int*, const int*, int, size_t, hipStream_t);
+template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*, const int*, int, size_t, hipStream_t);
 
 // ------------------------------------------------------------- launchers
 static inline dim3 node_grid2(const Consts& c, dim3 blk) {

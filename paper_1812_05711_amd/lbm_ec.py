@@ -87,6 +87,29 @@ def lib():
     L.lbm_ec_profile_begin.restype = ctypes.c_int
     L.lbm_ec_profile_end.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
     L.lbm_ec_profile_end.restype = ctypes.c_int
+    i32 = ctypes.c_int32
+    L.lbm_ec_batch_workspace_bytes.argtypes = [P, i32, i32, i32]
+    L.lbm_ec_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_ec_batch_create.argtypes = [i32, i32, i32, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.lbm_ec_batch_create.restype = ctypes.c_int
+    L.lbm_ec_batch_admit.argtypes = [vp, P, ctypes.c_int64, ctypes.POINTER(i32)]
+    L.lbm_ec_batch_admit.restype = ctypes.c_int
+    L.lbm_ec_batch_step.argtypes = [vp, ctypes.c_int64]
+    L.lbm_ec_batch_step.restype = ctypes.c_int
+    L.lbm_ec_batch_poll.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+    L.lbm_ec_batch_poll.restype = ctypes.c_int
+    L.lbm_ec_batch_steps_done.argtypes = [vp, i32]
+    L.lbm_ec_batch_steps_done.restype = ctypes.c_int64
+    L.lbm_ec_batch_fields.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.lbm_ec_batch_fields.restype = ctypes.c_int
+    L.lbm_ec_batch_history.argtypes = [vp, i32, dp, i32]
+    L.lbm_ec_batch_history.restype = ctypes.c_int
+    L.lbm_ec_batch_release.argtypes = [vp, i32]
+    L.lbm_ec_batch_release.restype = ctypes.c_int
+    L.lbm_ec_batch_free_bytes.argtypes = [vp]
+    L.lbm_ec_batch_free_bytes.restype = ctypes.c_size_t
+    L.lbm_ec_batch_destroy.argtypes = [vp]
+    L.lbm_ec_batch_destroy.restype = None
     L.lbm_ec_destroy.argtypes = [vp]
     L.lbm_ec_destroy.restype = None
     L.lbm_ec_last_error.argtypes = []
@@ -195,6 +218,96 @@ class Simulation:
     def close(self):
         if getattr(self, "_h", None):
             lib().lbm_ec_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_workspace_bytes(params_list, max_slots, hist_rows):
+    n = len(params_list)
+    arr = (Params * max(n, 1))(*params_list) if n else None
+    return int(lib().lbm_ec_batch_workspace_bytes(arr, n, int(max_slots), int(hist_rows)))
+
+
+class Batch:
+    """Many simulations advanced together (C ABI lbm_ec_batch_*).
+
+    The workspace is one torch uint8 tensor of `workspace_bytes`; the batch
+    runs on its own torch stream unless one is given.
+    """
+
+    def __init__(self, max_slots, workspace_bytes, precision="fp32_f64math", emit_every=100, hist_rows=256,
+                 device="cuda:0", stream=None):
+        self.device = torch.device(device)
+        self.precision = _PRECISION[precision] if isinstance(precision, str) else int(precision)
+        self.hist_rows = int(hist_rows)
+        self.emit_every = int(emit_every)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            _check(lib().lbm_ec_batch_create(int(max_slots), self.precision, self.emit_every, self.hist_rows,
+                                             ctypes.c_void_p(self.workspace.data_ptr()), int(workspace_bytes),
+                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._shape = {}
+
+    def admit(self, n_steps, **kw):
+        """Slot index, or None when no slot or workspace is free (EBUSY)."""
+        kw.setdefault("precision", self.precision)
+        p = make_params(**kw)
+        slot = ctypes.c_int32(-1)
+        code = lib().lbm_ec_batch_admit(self._h, ctypes.byref(p), int(n_steps), ctypes.byref(slot))
+        if code == EBUSY:
+            return None
+        _check(code)
+        self._shape[slot.value] = (p.ny, p.nx)
+        return slot.value
+
+    def step(self, n=1):
+        _check(lib().lbm_ec_batch_step(self._h, int(n)))
+        return self
+
+    def poll(self):
+        cap = 4096
+        buf = (ctypes.c_int32 * cap)()
+        nd = ctypes.c_int32(0)
+        _check(lib().lbm_ec_batch_poll(self._h, buf, cap, ctypes.byref(nd)))
+        return [buf[i] for i in range(nd.value)]
+
+    def steps_done(self, slot):
+        return int(lib().lbm_ec_batch_steps_done(self._h, int(slot)))
+
+    def fields(self, slot):
+        ny, nx = self._shape[slot]
+        out = {k: torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+               for k in ("rho", "ux", "uy", "rho_c", "phi")}
+        _check(lib().lbm_ec_batch_fields(self._h, int(slot), *[ctypes.c_void_p(out[k].data_ptr())
+                                                               for k in ("rho", "ux", "uy", "rho_c", "phi")]))
+        self.stream.synchronize()
+        return out
+
+    def history(self, slot):
+        import numpy as np
+
+        buf = (ctypes.c_double * (4 * self.hist_rows))()
+        _check(lib().lbm_ec_batch_history(self._h, int(slot), buf, self.hist_rows))
+        return np.frombuffer(buf, dtype=np.float64).reshape(self.hist_rows, 4).copy()
+
+    def release(self, slot):
+        _check(lib().lbm_ec_batch_release(self._h, int(slot)))
+        self._shape.pop(slot, None)
+
+    def free_bytes(self):
+        return int(lib().lbm_ec_batch_free_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_ec_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

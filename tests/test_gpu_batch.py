@@ -1,0 +1,119 @@
+"""Batched execution: every slot of a mixed batch computes exactly what the
+same simulation computes alone through lbm_ec_step (bitwise), slots stop at
+their own step counts, admission respects the workspace, and a slot admitted
+while others run is unaffected by them."""
+
+import numpy as np
+import pytest
+
+from gpu_util import errors, oracle_fields
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(T=200.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6, noise_amp=1e-3,
+            seed=181205711)
+MIX = [
+    (dict(BASE, nx=24, ny=10, T=150.0, instance_id=1), 30),
+    (dict(BASE, nx=61, ny=20, T=250.0, instance_id=2), 45),
+    (dict(BASE, nx=16, ny=40, C=1.0, instance_id=3), 17),
+    (dict(BASE, nx=80, ny=64, T=120.0, C=100.0, instance_id=4), 60),
+    (dict(BASE, nx=122, ny=100, instance_id=5, init_mode="eq29"), 33),
+]
+
+
+def _alone(kw, n, precision):
+    import torch
+
+    from paper_1812_05711_amd.lbm_ec import Simulation
+
+    sim = Simulation(device="cuda:0", precision=precision, **kw)
+    sim.step(n)
+    f = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    torch.cuda.synchronize()
+    sim.close()
+    return f
+
+
+def _batch(precision, max_slots=8, extra=1 << 20):
+    from paper_1812_05711_amd.lbm_ec import Batch, batch_workspace_bytes, make_params
+
+    ps = [make_params(precision=precision, **kw) for kw, _ in MIX]
+    ws = batch_workspace_bytes(ps, max_slots, 64) + extra
+    return Batch(max_slots, ws, precision=precision, emit_every=10, hist_rows=64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_f64math", "fp32"])
+def test_mix_equals_alone_bitwise(precision):
+    b = _batch(precision)
+    slots = [b.admit(n, **kw) for kw, n in MIX]
+    assert None not in slots
+    b.step(7)
+    # a late arrival joins while the others run
+    late_kw, late_n = dict(BASE, nx=40, ny=33, T=300.0, instance_id=9), 25
+    late = b.admit(late_n, **late_kw)
+    assert late is not None
+    b.step(100)
+    done = set(b.poll())
+    assert done == set(slots + [late])
+    for (kw, n), s in list(zip(MIX, slots)) + [((late_kw, late_n), late)]:
+        assert b.steps_done(s) == n
+        got = {k: v.cpu().numpy() for k, v in b.fields(s).items()}
+        ref = _alone(kw, n, precision)
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (precision, kw["nx"], kw["ny"], k)
+    b.close()
+
+
+def test_batch_slot_matches_oracle():
+    b = _batch("fp64")
+    kw, n = MIX[1]
+    s = b.admit(n, **kw)
+    other = b.admit(MIX[3][1], **MIX[3][0])
+    b.step(200)
+    assert set(b.poll()) == {s, other}
+    got = {k: v.cpu().numpy() for k, v in b.fields(s).items()}
+    e = errors(got, oracle_fields(kw, n))
+    assert max(e["rho"], e["u"], e["rho_c"], e["phi"]) <= 1e-11, e
+    b.close()
+
+
+def test_history_rows_match_fields():
+    b = _batch("fp64")
+    kw, n = MIX[3]
+    s = b.admit(n, **kw)
+    b.step(n)
+    b.poll()
+    h = b.history(s)
+    steps = h[:, 0]
+    assert list(steps[: n // 10]) == [10.0 * (r + 1) for r in range(n // 10)]
+    f = b.fields(s)
+    import math
+
+    from oracle import Params, lattice_constants
+
+    u0 = lattice_constants(Params(**kw)).u0
+    uy = f["uy"].cpu().numpy() * u0
+    row = n // 10 - 1  # n = 60 is a multiple of 10
+    assert math.isclose(h[row, 1], float(np.sqrt(np.mean(uy * uy))), rel_tol=1e-12)
+    b.close()
+
+
+def test_admission_respects_workspace_and_reuse():
+    from paper_1812_05711_amd.lbm_ec import Batch, batch_workspace_bytes, make_params
+
+    kw = dict(BASE, nx=64, ny=32)
+    one = batch_workspace_bytes([make_params(**kw)], 4, 8) - batch_workspace_bytes([], 4, 8)
+    ws = batch_workspace_bytes([], 4, 8) + 2 * one + 1024
+    b = Batch(4, ws, precision="fp64", emit_every=0, hist_rows=8)
+    a = b.admit(5, **kw)
+    c = b.admit(5, **dict(kw, instance_id=1))
+    assert a is not None and c is not None
+    assert b.admit(5, **dict(kw, instance_id=2)) is None  # workspace full: EBUSY
+    b.step(5)
+    assert set(b.poll()) == {a, c}
+    b.release(a)
+    d = b.admit(5, **dict(kw, instance_id=2))
+    assert d is not None
+    b.step(5)
+    assert b.poll() == [d]
+    b.close()
