@@ -2,7 +2,8 @@
 """Coupled-step throughput of the electroconvection time step on one MI355X.
 
 Workload (the bandwidth configuration): nx = ny = 4096, FP32-deviation
-storage, T = 500, C = 10, M = 10, Fe = 4000, Lambda = 1/4, Lambda_g = 1e-6,
+storage (collision arithmetic in FP64, the mode that meets the 1e-5 parity
+gate; --precision fp32 for FP32 arithmetic), T = 500, C = 10, M = 10, Fe = 4000, Lambda = 1/4, Lambda_g = 1e-6,
 tau+ = 0.8, hydrostatic initial state with seeded relative charge noise 1e-4.
 A step is one pass of the whole coupled path: charge gather and forward
 x-transform, x-mean Poisson mode, per-wavenumber solves, inverse transform,
@@ -18,6 +19,18 @@ Prints one JSON line:
   step_roofline  the whole step against the HBM roofline of its algorithmic
                  bytes (176 B/node FP32)
   cpu_baseline   the FP64 oracle on the host (same grid, two timed steps)
+  serve          the served stream: Poisson arrivals at 50 requests/s, ny in
+                 {64, 128, 256, 512} with weights 0.4 / 0.3 / 0.2 / 0.1, nx =
+                 smallest 5-smooth >= round(1.22 ny), T uniform in [120, 400],
+                 C in {1, 10, 100}, FP32 storage, 5000 steps per request,
+                 admission by workspace footprint; p50 / p99 latency from
+                 arrival to final fields (after the warm-up requests), runs/s
+  sweep          the batched T sweep: 64 instances, ny uniform in 64..256,
+                 nx = smallest 5-smooth >= round(1.22 ny), T uniform in
+                 [100, 250], C = 10, M = 10, FP32 storage, 20000 steps each,
+                 autotuned launch shapes, one batch (captured HIP graphs),
+                 against the same instances run one at a time through
+                 lbm_ec_step (timed over 1000 steps each, scaled to 20000)
 """
 
 import argparse
@@ -95,6 +108,43 @@ def cpu_baseline(nx, ny, steps=2):
                       f"({r['seconds']:.1f} s), single thread"}
 
 
+def sweep_section(steps, plain_steps):
+    import numpy as np
+
+    from paper_1812_05711_amd import sweep
+
+    cfgs = sweep.sweep_configs()
+    nodes = sum(c["nx"] * c["ny"] for c in cfgs)
+    log(f"sweep: {len(cfgs)} instances, {nodes} nodes, {steps} steps, batched")
+    r = sweep.run_batched(cfgs, steps)
+    log(f"sweep: batched {r['seconds']:.2f} s; plain, {plain_steps} steps each")
+    tp = sweep.run_plain(cfgs, plain_steps) * steps / plain_steps
+    T = [c["T"] for c in cfgs]
+    g = r["growth"]
+    order = np.argsort(T)
+    return {"instances": len(cfgs), "steps": steps, "nodes": nodes,
+            "batched_runs_per_s": len(cfgs) / r["seconds"], "plain_runs_per_s": len(cfgs) / tp,
+            "speedup": tp / r["seconds"], "batched_seconds": r["seconds"], "plain_seconds": tp,
+            "batched_mlups": nodes * steps / r["seconds"] / 1e6,
+            "plain_sample": f"{plain_steps} steps per instance, scaled to {steps}",
+            "tuning": list(r["tuning"]) if r["tuning"] else None,
+            "growth_rate_by_T": [[round(T[i], 2), round(g[i], 4)] for i in order]}
+
+
+def serve_section(n, warmup, budget_gb):
+    from paper_1812_05711_amd.serve import BatchBackend, make_requests, serve
+
+    reqs = make_requests(n, rate=50.0, steps=5000)
+    log(f"serve: {n} requests at 50/s, budget {budget_gb} GB")
+    be = BatchBackend(int(budget_gb * (1 << 30)), max_slots=512)
+    records, summary = serve(reqs, be, chunk=100, warmup=warmup, max_wall=600.0)
+    be.close()
+    summary.update({"rate_per_s": 50.0, "steps_per_request": 5000, "warmup_requests": warmup,
+                    "budget_bytes": int(budget_gb * (1 << 30)), "chunk_steps": 100})
+    log(f"serve: p50 {summary['p50_s']:.3f} s, p99 {summary['p99_s']:.3f} s, {summary['runs_per_s']:.1f} runs/s")
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,8 +152,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--nx", type=int, default=4096)
     ap.add_argument("--ny", type=int, default=4096)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_f64math", "fp64"])
+    ap.add_argument("--precision", default="fp32_f64math", choices=["fp32", "fp32_f64math", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--sweep-steps", type=int, default=20000)
+    ap.add_argument("--sweep-plain-steps", type=int, default=1000)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -156,10 +213,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp32_f64math": "f32 storage / f64 collision", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"coupled TRT-LBM / FFT-Poisson electroconvection step, {nx}x{ny}, "
-                               f"{'FP32-deviation' if args.precision == 'fp32' else 'FP64'} storage, "
+                               f"{'FP64' if args.precision == 'fp64' else 'FP32-deviation'} storage, "
                                "T=500 C=10 M=10 Fe=4000, seeded charge noise 1e-4",
                    "nx": nx, "ny": ny, "precision": args.precision},
         "roofline": {"bound": "hbm", "kernel": "collide-stream", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -172,6 +229,9 @@ def main():
     }
     del sim
     torch.cuda.empty_cache()
+    out["sweep"] = None if args.no_sweep else sweep_section(args.sweep_steps, args.sweep_plain_steps)
+    out["serve"] = None if args.no_serve else serve_section(args.serve_requests, args.serve_warmup,
+                                                            args.serve_budget_gb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nx, ny)
     else:

@@ -172,6 +172,13 @@ int lbm_ec_stats(lbm_ec_t* h, double* out);
 int lbm_ec_profile_begin(lbm_ec_t* h);
 int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 
+/* Launch shapes, which never change results: threads per x-transform block
+ * (64, 128 or 256) and the collide block shape (collide_bx x collide_by
+ * threads, product 64, 128 or 256).  Defaults 256 and 64 x 4.  Applies to the
+ * following steps; EINVAL for other values.  The autotuner in
+ * paper_1812_05711_amd/autotune.py picks them by timing. */
+int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by);
+
 /* Releases the handle (host memory only; the caller frees the workspace). */
 void lbm_ec_destroy(lbm_ec_t* h);
 
@@ -232,6 +239,10 @@ int lbm_ec_batch_fields(lbm_ec_batch_t* b, int32_t slot, double* rho, double* ux
  * last row the final step when that is not a multiple of emit_every; unused
  * rows are zero. */
 int lbm_ec_batch_history(lbm_ec_batch_t* b, int32_t slot, double* out, int32_t rows);
+
+/* Launch shapes for the batch's kernels (as lbm_ec_set_tuning); the graphs
+ * are re-captured at the next step. */
+int lbm_ec_batch_set_tuning(lbm_ec_batch_t* b, int32_t fft_threads, int32_t collide_bx, int32_t collide_by);
 
 /* Frees a slot and its workspace region (waits for the stream). */
 int lbm_ec_batch_release(lbm_ec_batch_t* b, int32_t slot);

@@ -1,0 +1,112 @@
+"""Autotuner for the launch shapes of the time step (they never change
+results): threads per x-transform block and the collide block shape.
+
+Candidates are timed with events on the batch's stream, on a throwaway batch
+of the same composition (so the real run is not advanced), and the best is
+cached in a JSON file keyed by the precision and the multiset of grid shapes.
+"""
+
+import hashlib
+import json
+import os
+
+FFT_THREADS = (64, 128, 256)
+COLLIDE_SHAPES = ((64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (256, 1), (32, 4), (32, 8))
+DEFAULT = (256, 64, 4)
+
+
+def cache_path():
+    return os.environ.get("LBM_EC_TUNING_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "lbm_ec_tuning.json"))
+
+
+def signature(configs):
+    shapes = sorted((c["nx"], c["ny"]) for c in configs)
+    key = json.dumps([configs[0].get("precision", "fp64"), shapes])
+    return hashlib.sha256(key.encode()).hexdigest()[:24]
+
+
+def _load():
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except Exception:
+        return {}
+
+
+def _store(cache):
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time_batch(b, steps):
+    import torch
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    b.step(8)  # capture and warm up
+    start.record(b.stream)
+    b.step(steps)
+    end.record(b.stream)
+    end.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
+    """Best (fft_threads, collide_bx, collide_by) for this batch composition."""
+    from .sweep import make_batch
+
+    sig = signature(configs)
+    cache = _load() if use_cache else {}
+    if sig in cache:
+        return tuple(cache[sig]["tuning"])
+    # enough steps for every candidate; the throwaway batch is never polled
+    n_cand = len(FFT_THREADS) + len(COLLIDE_SHAPES)
+    b, _ = make_batch(configs, steps=(steps + 8) * n_cand + 8, emit_every=0, device=device)
+    best_fft, best_t = DEFAULT[0], float("inf")
+    for ft in FFT_THREADS:
+        b.set_tuning(ft, DEFAULT[1], DEFAULT[2])
+        t = _time_batch(b, steps)
+        if t < best_t:
+            best_fft, best_t = ft, t
+    best_shape, best_t = DEFAULT[1:], float("inf")
+    for bx, by in COLLIDE_SHAPES:
+        b.set_tuning(best_fft, bx, by)
+        t = _time_batch(b, steps)
+        if t < best_t:
+            best_shape, best_t = (bx, by), t
+    b.close()
+    tuning = (best_fft, best_shape[0], best_shape[1])
+    cache[sig] = {"tuning": list(tuning), "ms_per_step": best_t}
+    if use_cache:
+        _store(cache)
+    return tuning
+
+
+def tune_single(sim, steps=16):
+    """Best launch shapes for one simulation (advances it by the timing steps)."""
+    import torch
+
+    best, best_t = DEFAULT, float("inf")
+    for ft in FFT_THREADS:
+        for bx, by in COLLIDE_SHAPES:
+            sim.set_tuning(ft, bx, by)
+            sim.step(2)
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(sim.stream)
+            sim.step(steps)
+            end.record(sim.stream)
+            end.synchronize()
+            t = start.elapsed_time(end) / steps
+            if t < best_t:
+                best, best_t = (ft, bx, by), t
+    sim.set_tuning(*best)
+    return best, best_t

@@ -157,6 +157,7 @@ struct Profiler {
 
 struct lbm_ec {
   lbm_ec_params p;
+  ec::Tuning tu;
   Profiler prof;
   Layout L;
   ec::Consts c;
@@ -353,10 +354,10 @@ int prof_mark(lbm_ec* h, int cls) {
 
 template <typename T>
 int poisson_chain(lbm_ec* h, int mode, int src) {
-  EC_TIMED(h, KC_FORWARD, (ec::launch_forward<T>(h->c, h->b, h->plan, mode, src, h->s)));
+  EC_TIMED(h, KC_FORWARD, (ec::launch_forward<T>(h->c, h->b, h->plan, mode, src, h->tu, h->s)));
   EC_TIMED(h, KC_MEAN, (ec::launch_mean_mode<T>(h->c, h->b, h->s)));
   EC_TIMED(h, KC_TRIDIAG, (ec::launch_tridiag<T>(h->c, h->b, h->s)));
-  EC_TIMED(h, KC_INVERSE, (ec::launch_inverse<T>(h->c, h->b, h->plan, h->s)));
+  EC_TIMED(h, KC_INVERSE, (ec::launch_inverse<T>(h->c, h->b, h->plan, h->tu, h->s)));
   return LBM_EC_OK;
 }
 
@@ -370,7 +371,7 @@ int init_state(lbm_ec* h) {
   // step 0: charge of the initial populations, Poisson, first collision
   // (no streaming) into buffer 0, with the moments of state 0
   if ((rc = poisson_chain<T>(h, 1, 1))) return rc;
-  EC_HIP((ec::launch_collide<T, C>(h->c, h->b, false, true, 1, 0, h->s)));
+  EC_HIP((ec::launch_collide<T, C>(h->c, h->b, false, true, 1, 0, h->tu, h->s)));
   h->cur = 0;
   h->steps = 0;
   return LBM_EC_OK;
@@ -382,7 +383,7 @@ int run_steps(lbm_ec* h, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const int src = h->cur, dst = 1 - h->cur;
     if ((rc = poisson_chain<T>(h, 0, src))) return rc;
-    EC_TIMED(h, KC_COLLIDE, (ec::launch_collide<T, C>(h->c, h->b, true, k == n - 1, src, dst, h->s)));
+    EC_TIMED(h, KC_COLLIDE, (ec::launch_collide<T, C>(h->c, h->b, true, k == n - 1, src, dst, h->tu, h->s)));
     h->cur = dst;
     h->steps += 1;
   }
@@ -476,6 +477,7 @@ struct lbm_ec_batch {
   bool dirty;
   hipGraphExec_t g_many, g_one;
   bool have_graphs;
+  ec::Tuning tu;
 };
 
 namespace {
@@ -533,7 +535,7 @@ int capture(lbm_ec_batch* B, int steps, hipGraphExec_t* out) {
   EC_HIP(hipStreamBeginCapture(B->s, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < steps && le == hipSuccess; ++k)
-    le = ec::launch_batch_step<T, C>(B->d_desc, B->d_off, B->totals, (int)B->order.size(), B->lds, B->s);
+    le = ec::launch_batch_step<T, C>(B->d_desc, B->d_off, B->totals, (int)B->order.size(), B->lds, B->tu, B->s);
   hipError_t ee = hipStreamEndCapture(B->s, &g);
   if (le != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture launch: ") + hipGetErrorString(le));
   if (ee != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture: ") + hipGetErrorString(ee));
@@ -551,6 +553,7 @@ int pull_state(lbm_ec_batch* B) {
   EC_HIP(hipMemcpyAsync(D.data(), B->d_desc, sizeof(ec::SlotDesc) * ns, hipMemcpyDeviceToHost, B->s));
   EC_HIP(hipStreamSynchronize(B->s));
   for (int q = 0; q < ns; ++q) {
+    if (B->order[q] < 0) continue;  // released since the tables were built
     Slot& sl = B->slots[B->order[q]];
     sl.inst.cur = D[q].cur;
     sl.inst.steps = D[q].steps_done;
@@ -590,7 +593,7 @@ int rebuild(lbm_ec_batch* B) {
     B->lds = std::max(B->lds, lds);
     for (int k = 0; k < ec::BK_COUNT; ++k) {
       off[(size_t)k * (ns + 1) + q] = B->totals[k];
-      B->totals[k] += ec::batch_blocks(d.c, k);
+      B->totals[k] += ec::batch_blocks(d.c, k, B->tu);
     }
   }
   for (int k = 0; k < ec::BK_COUNT; ++k) off[(size_t)k * (ns + 1) + ns] = B->totals[k];
@@ -774,6 +777,10 @@ int lbm_ec_batch_release(lbm_ec_batch_t* B, int32_t slot) {
   for (hipEvent_t e : sl.inst.prof.ev) (void)hipEventDestroy(e);
   heap_free(B, sl.off, sl.bytes);
   sl = Slot();
+  // the device tables still list this slot until the next rebuild: make sure
+  // its entry is never read back into a simulation admitted to the same slot
+  for (int& q : B->order)
+    if (q == slot) q = -1;
   B->dirty = true;
   return LBM_EC_OK;
 }
@@ -793,6 +800,36 @@ void lbm_ec_batch_destroy(lbm_ec_batch_t* B) {
     for (hipEvent_t e : sl.inst.prof.ev) (void)hipEventDestroy(e);
   if (B->own_stream) (void)hipStreamDestroy(B->s);
   delete B;
+}
+
+static int check_tuning(int32_t fft_threads, int32_t bx, int32_t by) {
+  if (fft_threads != 64 && fft_threads != 128 && fft_threads != 256)
+    return fail(LBM_EC_EINVAL, "fft_threads must be 64, 128 or 256");
+  const int t = bx * by;
+  if (bx < 1 || by < 1 || (t != 64 && t != 128 && t != 256))
+    return fail(LBM_EC_EINVAL, "collide block bx * by must be 64, 128 or 256");
+  return LBM_EC_OK;
+}
+
+int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by) {
+  if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
+  int rc = check_tuning(fft_threads, collide_bx, collide_by);
+  if (rc) return rc;
+  h->tu.fft_threads = fft_threads;
+  h->tu.cbx = collide_bx;
+  h->tu.cby = collide_by;
+  return LBM_EC_OK;
+}
+
+int lbm_ec_batch_set_tuning(lbm_ec_batch_t* B, int32_t fft_threads, int32_t collide_bx, int32_t collide_by) {
+  if (!B) return fail(LBM_EC_EINVAL, "NULL argument");
+  int rc = check_tuning(fft_threads, collide_bx, collide_by);
+  if (rc) return rc;
+  B->tu.fft_threads = fft_threads;
+  B->tu.cbx = collide_bx;
+  B->tu.cby = collide_by;
+  B->dirty = true;
+  return LBM_EC_OK;
 }
 
 int lbm_ec_params_default(lbm_ec_params* p) {

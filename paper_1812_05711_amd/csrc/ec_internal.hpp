@@ -111,18 +111,25 @@ struct SlotDesc {
   double* hist;        // [hist_cap][4]: step, rms u_y, max |u|, sum of rho_c (lattice units)
 };
 
+// Launch shapes that do not change results: threads per x-transform block
+// and the collide block (bx x by threads, bx * by in {64, 128, 256}).
+struct Tuning {
+  int fft_threads = 256;
+  int cbx = 64, cby = 4;
+};
+
 // Batched kernels; slot s owns the blocks [off[k][s], off[k][s+1]) of launch k.
 enum BatchKernel { BK_FORWARD = 0, BK_MEAN, BK_TRI_LOCAL, BK_TRI_REDUCED, BK_INVERSE, BK_COLLIDE, BK_STATS, BK_COUNT };
 
 // Blocks that kernel k uses for one instance.
-int batch_blocks(const Consts& c, int k);
+int batch_blocks(const Consts& c, int k, const Tuning& tu);
 
 // Enqueues one batched step (all kernels, then the device-side advance) for
 // ns slots.  d_off holds BK_COUNT rows of ns + 1 offsets; totals[k] is the
 // block count of launch k; lds the dynamic LDS of the transforms.
 template <typename T, typename C>
 hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
-                             hipStream_t s);
+                             const Tuning& tu, hipStream_t s);
 
 // Kernel launchers (ec_kernels.hip).  All enqueue on `s` and return the
 // launch status.
@@ -134,7 +141,7 @@ hipError_t launch_init_populations(const Consts& c, const Bufs& b, int dst, hipS
 // 2: read the charge deviation field held in b.mom (plane 3)
 template <typename T>
 hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src,
-                          hipStream_t s);
+                          const Tuning& tu, hipStream_t s);
 template <typename T>
 hipError_t launch_mean_mode(const Consts& c, const Bufs& b, hipStream_t s);
 // per-wavenumber y solves, m >= 1: chunk-local solves, then the interface
@@ -142,11 +149,11 @@ hipError_t launch_mean_mode(const Consts& c, const Bufs& b, hipStream_t s);
 template <typename T>
 hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s);
 template <typename T>
-hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, hipStream_t s);
+hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, const Tuning& tu, hipStream_t s);
 // T: storage type of the populations, C: arithmetic type of the collision
 template <typename T, typename C>
 hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst,
-                          hipStream_t s);
+                          const Tuning& tu, hipStream_t s);
 template <typename T>
 hipError_t launch_fields(const Consts& c, const Bufs& b, double* rho, double* ux, double* uy,
                          double* rho_c, double* phi, hipStream_t s);

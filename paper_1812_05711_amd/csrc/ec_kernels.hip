@@ -1035,7 +1035,7 @@ __global__ void __launch_bounds__(256) kb_collide(const SlotDesc* __restrict__ D
   const SlotDesc& d = D[s];
   if (!d.active) return;
   const int lb = blockIdx.x - off[s];
-  const int nbx = (d.c.nx + 63) / 64;
+  const int nbx = (d.c.nx + blockDim.x - 1) / blockDim.x;
   const int src = d.cur, dst = 1 - d.cur;
   collide_body<T, C, true>(d.c, (const T*)d.b.f[src], (const T*)d.b.g[src], (T*)d.b.f[dst], (T*)d.b.g[dst],
                            (const T*)d.b.phi, (const T*)d.b.rows, d.b.rowsd, slot_emits(d) ? d.b.mom : nullptr,
@@ -1092,7 +1092,7 @@ __global__ void kb_advance(SlotDesc* __restrict__ D, int ns) {
   if (d.steps_done >= d.steps_target) d.active = 0;
 }
 
-int batch_blocks(const Consts& c, int k) {
+int batch_blocks(const Consts& c, int k, const Tuning& tu) {
   const int nm = c.M - 1;
   switch (k) {
     case BK_FORWARD:
@@ -1100,7 +1100,7 @@ int batch_blocks(const Consts& c, int k) {
     case BK_MEAN: return 1;
     case BK_TRI_LOCAL: return nm > 0 ? ((nm + 63) / 64) * c.NC : 0;
     case BK_TRI_REDUCED: return (nm > 0 && c.NC >= 2) ? (nm + 63) / 64 : 0;
-    case BK_COLLIDE: return ((c.nx + 63) / 64) * ((c.ny + 3) / 4);
+    case BK_COLLIDE: return ((c.nx + tu.cbx - 1) / tu.cbx) * ((c.ny + tu.cby - 1) / tu.cby);
     case BK_STATS: return 1;
   }
   return 0;
@@ -1108,11 +1108,11 @@ int batch_blocks(const Consts& c, int k) {
 
 template <typename T, typename C>
 hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
-                             hipStream_t s) {
+                             const Tuning& tu, hipStream_t s) {
   const int row = ns + 1;
   SlotDesc* D = const_cast<SlotDesc*>(d_desc);
   if (totals[BK_FORWARD])
-    hipLaunchKernelGGL(kb_forward<T>, dim3(totals[BK_FORWARD]), dim3(256), lds, s, d_desc, d_off + BK_FORWARD * row, ns);
+    hipLaunchKernelGGL(kb_forward<T>, dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s, d_desc, d_off + BK_FORWARD * row, ns);
   if (totals[BK_MEAN])
     hipLaunchKernelGGL(kb_mean_mode, dim3(totals[BK_MEAN]), dim3(1024), 0, s, d_desc, d_off + BK_MEAN * row, ns);
   if (totals[BK_TRI_LOCAL])
@@ -1122,9 +1122,9 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
     hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(64), 0, s, d_desc,
                        d_off + BK_TRI_REDUCED * row, ns);
   if (totals[BK_INVERSE])
-    hipLaunchKernelGGL(kb_inverse<T>, dim3(totals[BK_INVERSE]), dim3(256), lds, s, d_desc, d_off + BK_INVERSE * row, ns);
+    hipLaunchKernelGGL(kb_inverse<T>, dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s, d_desc, d_off + BK_INVERSE * row, ns);
   if (totals[BK_COLLIDE])
-    hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(64, 4), 0, s, d_desc,
+    hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(tu.cbx, tu.cby), 0, s, d_desc,
                        d_off + BK_COLLIDE * row, ns);
   if (totals[BK_STATS])
     hipLaunchKernelGGL(kb_stats, dim3(totals[BK_STATS]), dim3(256), 0, s, D, d_off + BK_STATS * row, ns);
@@ -1132,9 +1132,12 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
   return hipGetLastError();
 }
 
-template hipError_t launch_batch_step<double, double>(const SlotDesc*, const int*, const int*, int, size_t, hipStream_t);
-template hipError_t launch_batch_step<float, float>(const SlotDesc*, const int*, const int*, int, size_t, hipStream_t);
-template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*, const int*, int, size_t, hipStream_t);
+template hipError_t launch_batch_step<double, double>(const SlotDesc*, const int*, const int*, int, size_t,
+                                                     const Tuning&, hipStream_t);
+template hipError_t launch_batch_step<float, float>(const SlotDesc*, const int*, const int*, int, size_t,
+                                                   const Tuning&, hipStream_t);
+template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*, const int*, int, size_t,
+                                                    const Tuning&, hipStream_t);
 
 // ------------------------------------------------------------- launchers
 static inline dim3 node_grid2(const Consts& c, dim3 blk) {
@@ -1157,8 +1160,9 @@ hipError_t launch_init_populations(const Consts& c, const Bufs& b, int dst, hipS
 }
 
 template <typename T>
-hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src, hipStream_t s) {
-  dim3 blk(256), grd((c.ny + 1) / 2);
+hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src, const Tuning& tu,
+                          hipStream_t s) {
+  dim3 blk(tu.fft_threads), grd((c.ny + 1) / 2);
   const size_t lds = fft_lds_bytes<T>(pl.n);
   const T* G = (const T*)b.g[src];
   const T* rows = (const T*)b.rows;
@@ -1195,8 +1199,8 @@ hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, hipStream_t s) {
-  dim3 blk(256), grd((c.ny + 1) / 2);
+hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, const Tuning& tu, hipStream_t s) {
+  dim3 blk(tu.fft_threads), grd((c.ny + 1) / 2);
   const size_t lds = fft_lds_bytes<T>(pl.n);
   hipLaunchKernelGGL(k_inverse<T>, grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
                      (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
@@ -1204,8 +1208,9 @@ hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, hip
 }
 
 template <typename T, typename C>
-hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst, hipStream_t s) {
-  dim3 blk(64, 4);
+hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst,
+                          const Tuning& tu, hipStream_t s) {
+  dim3 blk(tu.cbx, tu.cby);
   dim3 grd = node_grid2(c, blk);
   const T* Fin = (const T*)b.f[src];
   const T* Gin = (const T*)b.g[src];
@@ -1248,10 +1253,11 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
 #define EC_INSTANTIATE(T)                                                                                   \
   template hipError_t launch_init_charge<T>(const Consts&, const Bufs&, hipStream_t);                       \
   template hipError_t launch_init_populations<T>(const Consts&, const Bufs&, int, hipStream_t);             \
-  template hipError_t launch_forward<T>(const Consts&, const Bufs&, const FftPlan&, int, int, hipStream_t); \
+  template hipError_t launch_forward<T>(const Consts&, const Bufs&, const FftPlan&, int, int, const Tuning&,   \
+                                       hipStream_t);                                                        \
   template hipError_t launch_mean_mode<T>(const Consts&, const Bufs&, hipStream_t);                         \
   template hipError_t launch_tridiag<T>(const Consts&, const Bufs&, hipStream_t);                           \
-  template hipError_t launch_inverse<T>(const Consts&, const Bufs&, const FftPlan&, hipStream_t);           \
+  template hipError_t launch_inverse<T>(const Consts&, const Bufs&, const FftPlan&, const Tuning&, hipStream_t); \
   template hipError_t launch_fields<T>(const Consts&, const Bufs&, double*, double*, double*, double*,       \
                                        double*, hipStream_t);                                               \
   template hipError_t launch_charge_in<T>(const Consts&, const Bufs&, const double*, hipStream_t);          \
@@ -1259,8 +1265,11 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
 
 EC_INSTANTIATE(double)
 EC_INSTANTIATE(float)
-template hipError_t launch_collide<double, double>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);
-template hipError_t launch_collide<float, float>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);
-template hipError_t launch_collide<float, double>(const Consts&, const Bufs&, bool, bool, int, int, hipStream_t);
+template hipError_t launch_collide<double, double>(const Consts&, const Bufs&, bool, bool, int, int, const Tuning&,
+                                                  hipStream_t);
+template hipError_t launch_collide<float, float>(const Consts&, const Bufs&, bool, bool, int, int, const Tuning&,
+                                                hipStream_t);
+template hipError_t launch_collide<float, double>(const Consts&, const Bufs&, bool, bool, int, int, const Tuning&,
+                                                 hipStream_t);
 
 }  // namespace ec

@@ -110,6 +110,10 @@ def lib():
     L.lbm_ec_batch_free_bytes.restype = ctypes.c_size_t
     L.lbm_ec_batch_destroy.argtypes = [vp]
     L.lbm_ec_batch_destroy.restype = None
+    L.lbm_ec_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.lbm_ec_set_tuning.restype = ctypes.c_int
+    L.lbm_ec_batch_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.lbm_ec_batch_set_tuning.restype = ctypes.c_int
     L.lbm_ec_destroy.argtypes = [vp]
     L.lbm_ec_destroy.restype = None
     L.lbm_ec_last_error.argtypes = []
@@ -201,6 +205,9 @@ class Simulation:
             _check(code)
         names = ["steps", "mass_dev", "charge", "rms_uy", "max_u", "min_rho_c", "bad", "max_ex"]
         return dict(zip(names, list(buf))), code == OK
+
+    def set_tuning(self, fft_threads=256, collide_bx=64, collide_by=4):
+        _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
 
     KERNEL_CLASSES = ("forward", "mean_mode", "tridiag", "inverse", "collide")
 
@@ -297,6 +304,9 @@ class Batch:
         buf = (ctypes.c_double * (4 * self.hist_rows))()
         _check(lib().lbm_ec_batch_history(self._h, int(slot), buf, self.hist_rows))
         return np.frombuffer(buf, dtype=np.float64).reshape(self.hist_rows, 4).copy()
+
+    def set_tuning(self, fft_threads=256, collide_bx=64, collide_by=4):
+        _check(lib().lbm_ec_batch_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
 
     def release(self, slot):
         _check(lib().lbm_ec_batch_release(self._h, int(slot)))

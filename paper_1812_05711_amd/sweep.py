@@ -1,0 +1,110 @@
+"""T sweeps for locating the electroconvective threshold: many uneven
+instances advanced as one batch (paper section V.2: the threshold T_c is
+where perturbations stop decaying).
+
+Each instance is a channel of ny rows with nx the smallest 5-smooth length
+not below round(1.22 ny) (the aspect ratio 1.22 of the paper's domain), its
+own T and seed; all share C, M, Fe and the precision.  The growth rate of an
+instance is the least-squares slope of ln(rms u_y) against t / t0 (t0 =
+H^2 / K, the ionic time) over the second half of its run, from the rows the
+batch records every `emit_every` steps.
+"""
+
+import time
+
+import numpy as np
+
+from . import autotune
+from .lbm_ec import Batch, Simulation, batch_workspace_bytes, make_params
+
+
+def five_smooth_at_least(n: int) -> int:
+    m = max(1, int(n))
+    while True:
+        k = m
+        for p in (2, 3, 5):
+            while k % p == 0:
+                k //= p
+        if k == 1:
+            return m
+        m += 1
+
+
+def sweep_configs(n=64, seed=181205711, ny_range=(64, 256), T_range=(100.0, 250.0), C=10.0, M=10.0, Fe=4000.0,
+                  tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6, noise_amp=1e-3, precision="fp32_f64math"):
+    """The seeded instance list of a sweep (dicts for make_params)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        ny = int(rng.integers(ny_range[0], ny_range[1] + 1))
+        nx = five_smooth_at_least(round(1.22 * ny))
+        T = float(rng.uniform(*T_range))
+        out.append(dict(nx=nx, ny=ny, T=T, C=C, M=M, Fe=Fe, tau_plus=tau_plus, Lambda=Lambda, Lambda_g=Lambda_g,
+                        noise_amp=noise_amp, seed=seed, instance_id=i, precision=precision))
+    return out
+
+
+def ionic_time(cfg):
+    nu = (cfg["tau_plus"] - 0.5) / 3.0
+    K = nu * cfg["T"] / cfg["M"] ** 2
+    return cfg["ny"] ** 2 / K
+
+
+def growth_rate(history, t0):
+    """Slope of ln(rms u_y) versus t / t0 over the second half of the rows."""
+    rows = history[history[:, 0] > 0]
+    if len(rows) < 4:
+        return float("nan")
+    rows = rows[np.argsort(rows[:, 0])]
+    h = len(rows) // 2
+    t = rows[h:, 0] / t0
+    a = np.log(np.maximum(rows[h:, 1], 1e-300))
+    return float(np.polyfit(t, a, 1)[0])
+
+
+def make_batch(configs, steps, emit_every=100, device="cuda:0", tuning=None):
+    hist_rows = steps // max(emit_every, 1) + 2
+    params = [make_params(**c) for c in configs]
+    ws = batch_workspace_bytes(params, len(configs), hist_rows) + (1 << 20)
+    b = Batch(len(configs), ws, precision=configs[0]["precision"], emit_every=emit_every, hist_rows=hist_rows,
+              device=device)
+    if tuning is not None:
+        b.set_tuning(*tuning)
+    slots = [b.admit(steps, **c) for c in configs]
+    if None in slots:
+        raise RuntimeError("batch workspace too small")
+    return b, slots
+
+
+def run_batched(configs, steps, emit_every=100, device="cuda:0", tune=True):
+    """Advances every instance `steps` steps as one batch.  Returns the wall
+    time of the stepping (creation excluded), the growth rates, the tuning."""
+    tuning = autotune.tune_batch(configs, device=device) if tune else None
+    b, slots = make_batch(configs, steps, emit_every, device, tuning)
+    b.stream.synchronize()
+    t = time.perf_counter()
+    b.step(steps)
+    b.stream.synchronize()
+    dt = time.perf_counter() - t
+    done = b.poll()
+    assert sorted(done) == sorted(slots)
+    rates = [growth_rate(b.history(s), ionic_time(c)) for s, c in zip(slots, configs)]
+    b.close()
+    return dict(seconds=dt, growth=rates, tuning=tuning)
+
+
+def run_plain(configs, steps, device="cuda:0"):
+    """Each instance alone through lbm_ec_step, one after another.  Returns
+    the summed stepping time (creation excluded)."""
+    import torch
+
+    total = 0.0
+    for c in configs:
+        sim = Simulation(device=device, **c)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t
+        sim.close()
+    return total

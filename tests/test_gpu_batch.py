@@ -112,8 +112,13 @@ def test_admission_respects_workspace_and_reuse():
     b.step(5)
     assert set(b.poll()) == {a, c}
     b.release(a)
-    d = b.admit(5, **dict(kw, instance_id=2))
+    d = b.admit(7, **dict(kw, instance_id=2))
     assert d is not None
-    b.step(5)
+    assert b.steps_done(d) == 0  # a reused slot starts from its own state
+    b.step(7)
     assert b.poll() == [d]
+    got = {k: v.cpu().numpy() for k, v in b.fields(d).items()}
+    ref = _alone(dict(kw, instance_id=2), 7, "fp64")
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
     b.close()
