@@ -154,6 +154,7 @@ def main():
     ap.add_argument("--ny", type=int, default=4096)
     ap.add_argument("--precision", default="fp32_f64math", choices=["fp32", "fp32_f64math", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600)
@@ -176,6 +177,12 @@ def main():
     log(f"create {nx}x{ny} {args.precision}")
     sim = Simulation(device="cuda:0", nx=nx, ny=ny, precision=args.precision, **WORKLOAD)
     torch.cuda.synchronize()
+    tuning = None
+    if not args.no_tune:
+        from paper_1812_05711_amd import autotune
+
+        tuning, t_ms = autotune.tune_single(sim, steps=8)
+        log(f"tuned launch shapes {tuning} ({t_ms:.3f} ms/step while tuning)")
     log(f"warmup {args.warmup} steps")
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -225,6 +232,7 @@ def main():
         "step_roofline": {"algorithmic_bytes_per_node": STEP_BYTES_PER_NODE[args.precision],
                           "roofline_mlups": roofline_mlups, "frac": mlups / roofline_mlups},
         "kernels": kernels,
+        "tuning": list(tuning) if tuning else None,
         "healthy": bool(healthy),
     }
     del sim
