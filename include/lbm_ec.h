@@ -173,7 +173,7 @@ int lbm_ec_profile_begin(lbm_ec_t* h);
 int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 
 /* Launch shapes, which never change results: threads per x-transform block
- * (64, 128 or 256) and the collide block shape (collide_bx x collide_by
+ * (64, 128, 256, 512 or 1024) and the collide block shape (collide_bx x collide_by
  * threads, product 64, 128 or 256).  Defaults 256 and 64 x 4.  Applies to the
  * following steps; EINVAL for other values.  The autotuner in
  * paper_1812_05711_amd/autotune.py picks them by timing. */

@@ -803,8 +803,8 @@ void lbm_ec_batch_destroy(lbm_ec_batch_t* B) {
 }
 
 static int check_tuning(int32_t fft_threads, int32_t bx, int32_t by) {
-  if (fft_threads != 64 && fft_threads != 128 && fft_threads != 256)
-    return fail(LBM_EC_EINVAL, "fft_threads must be 64, 128 or 256");
+  if (fft_threads != 64 && fft_threads != 128 && fft_threads != 256 && fft_threads != 512 && fft_threads != 1024)
+    return fail(LBM_EC_EINVAL, "fft_threads must be 64, 128, 256, 512 or 1024");
   const int t = bx * by;
   if (bx < 1 || by < 1 || (t != 64 && t != 128 && t != 256))
     return fail(LBM_EC_EINVAL, "collide block bx * by must be 64, 128 or 256");

@@ -234,6 +234,11 @@ __device__ double block_sum(double v, double* red) {
 __device__ __forceinline__ int wrap_m(int x, int nx) { return x == 0 ? nx - 1 : x - 1; }
 __device__ __forceinline__ int wrap_p(int x, int nx) { return x == nx - 1 ? 0 : x + 1; }
 
+// The pulls below choose their source addresses with selects instead of
+// branches, so that all nine loads of a node are issued before the first one
+// is used (branches around loads serialise them on memory latency).  Offsets
+// inside a plane fit 32 bits (nx ny <= 2^31 and P < nx + 64).
+
 // Pre-collision charge populations at (x, j), pulled from the post-collision
 // deviations G with the electrode conditions (Table I read as: injector
 // anti-bounce-back fixing rho_c = rho0, collector zero normal gradient).
@@ -242,32 +247,33 @@ __device__ __forceinline__ void pull_g(const Consts& c, const T* __restrict__ G,
                                        int x, int j, T g[9]) {
   const size_t plane = (size_t)c.ny * c.P;
   const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
-  const size_t row = (size_t)j * c.P;
-  g[0] = G[row + x];
-  g[1] = G[plane + row + xm];
-  g[3] = G[3 * plane + row + xp];
-  if (j > 0) {
-    const size_t rb = row - c.P;
-    const T ua = rows[ROW_DG_UP_AXIS * c.ny + j], ud = rows[ROW_DG_UP_DIAG * c.ny + j];
-    g[2] = G[2 * plane + rb + x] + ua;
-    g[5] = G[5 * plane + rb + xm] + ud;
-    g[6] = G[6 * plane + rb + xp] + ud;
-  } else {
-    g[2] = -G[4 * plane + row + x] + T(c.g_abb_axis);
-    g[5] = -G[7 * plane + row + x] + T(c.g_abb_diag);
-    g[6] = -G[8 * plane + row + x] + T(c.g_abb_diag);
-  }
-  if (j < c.ny - 1) {
-    const size_t ra = row + c.P;
-    const T da = rows[ROW_DG_DN_AXIS * c.ny + j], dd = rows[ROW_DG_DN_DIAG * c.ny + j];
-    g[4] = G[4 * plane + ra + x] + da;
-    g[7] = G[7 * plane + ra + xp] + dd;
-    g[8] = G[8 * plane + ra + xm] + dd;
-  } else {
-    g[4] = G[4 * plane + row + x];
-    g[7] = G[7 * plane + row + xp];
-    g[8] = G[8 * plane + row + xm];
-  }
+  const bool lo = j > 0, hi = j < c.ny - 1;
+  const unsigned row = (unsigned)j * (unsigned)c.P;
+  const unsigned rb = lo ? row - c.P : row, ra = hi ? row + c.P : row;
+  // below the node: streamed from row j-1, or reflected at the injector
+  const T* p2 = G + (lo ? 2 : 4) * plane;
+  const T* p5 = G + (lo ? 5 : 7) * plane;
+  const T* p6 = G + (lo ? 6 : 8) * plane;
+  const unsigned o2 = rb + x, o5 = rb + (lo ? xm : x), o6 = rb + (lo ? xp : x);
+  // above the node: streamed from row j+1, or the same-row neighbours at the
+  // collector (zero normal gradient)
+  const unsigned o4 = ra + x, o7 = ra + xp, o8 = ra + xm;
+  const T a0 = G[row + x];
+  const T a1 = G[plane + row + xm];
+  const T a3 = G[3 * plane + row + xp];
+  const T a2 = p2[o2], a5 = p5[o5], a6 = p6[o6];
+  const T a4 = G[4 * plane + o4], a7 = G[7 * plane + o7], a8 = G[8 * plane + o8];
+  const T ua = rows[ROW_DG_UP_AXIS * c.ny + j], ud = rows[ROW_DG_UP_DIAG * c.ny + j];
+  const T da = rows[ROW_DG_DN_AXIS * c.ny + j], dd = rows[ROW_DG_DN_DIAG * c.ny + j];
+  g[0] = a0;
+  g[1] = a1;
+  g[3] = a3;
+  g[2] = lo ? a2 + ua : -a2 + T(c.g_abb_axis);
+  g[5] = lo ? a5 + ud : -a5 + T(c.g_abb_diag);
+  g[6] = lo ? a6 + ud : -a6 + T(c.g_abb_diag);
+  g[4] = hi ? a4 + da : a4;
+  g[7] = hi ? a7 + dd : a7;
+  g[8] = hi ? a8 + dd : a8;
 }
 
 // Pre-collision fluid populations at (x, j) with halfway bounce-back at both
@@ -277,30 +283,24 @@ template <typename T>
 __device__ __forceinline__ void pull_f(const Consts& c, const T* __restrict__ F, int x, int j, T f[9]) {
   const size_t plane = (size_t)c.ny * c.P;
   const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
-  const size_t row = (size_t)j * c.P;
+  const bool lo = j > 0, hi = j < c.ny - 1;
+  const unsigned row = (unsigned)j * (unsigned)c.P;
+  const unsigned rb = lo ? row - c.P : row, ra = hi ? row + c.P : row;
+  const T* p2 = F + (lo ? 2 : 4) * plane;
+  const T* p5 = F + (lo ? 5 : 7) * plane;
+  const T* p6 = F + (lo ? 6 : 8) * plane;
+  const T* p4 = F + (hi ? 4 : 2) * plane;
+  const T* p7 = F + (hi ? 7 : 5) * plane;
+  const T* p8 = F + (hi ? 8 : 6) * plane;
   f[0] = F[row + x];
   f[1] = F[plane + row + xm];
   f[3] = F[3 * plane + row + xp];
-  if (j > 0) {
-    const size_t rb = row - c.P;
-    f[2] = F[2 * plane + rb + x];
-    f[5] = F[5 * plane + rb + xm];
-    f[6] = F[6 * plane + rb + xp];
-  } else {
-    f[2] = F[4 * plane + row + x];
-    f[5] = F[7 * plane + row + x];
-    f[6] = F[8 * plane + row + x];
-  }
-  if (j < c.ny - 1) {
-    const size_t ra = row + c.P;
-    f[4] = F[4 * plane + ra + x];
-    f[7] = F[7 * plane + ra + xp];
-    f[8] = F[8 * plane + ra + xm];
-  } else {
-    f[4] = F[2 * plane + row + x];
-    f[7] = F[5 * plane + row + x];
-    f[8] = F[6 * plane + row + x];
-  }
+  f[2] = p2[rb + x];
+  f[5] = p5[rb + (lo ? xm : x)];
+  f[6] = p6[rb + (lo ? xp : x)];
+  f[4] = p4[ra + x];
+  f[7] = p7[ra + (hi ? xp : x)];
+  f[8] = p8[ra + (hi ? xm : x)];
 }
 
 template <typename T>
@@ -309,6 +309,56 @@ __device__ __forceinline__ void local_pop(const Consts& c, const T* __restrict__
   const size_t idx = (size_t)j * c.P + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) a[i] = A[i * plane + idx];
+}
+
+// Charge density deviation rho_c - r at (x, j) at the start of the step:
+// MODE 0 pulls the post-collision populations (the streaming of Eq. 9),
+// MODE 1 sums the populations at the node, MODE 2 reads a given FP64 field.
+template <typename T, int MODE>
+__device__ __forceinline__ T charge_at(const Consts& c, const T* __restrict__ G, const T* __restrict__ rows,
+                                       const double* __restrict__ drc_field, int x, int j) {
+  if (MODE == 2) return T(drc_field[(size_t)j * c.nx + x]);
+  T g[9];
+  if (MODE == 0)
+    pull_g<T>(c, G, rows, x, j, g);
+  else
+    local_pop<T>(c, G, x, j, g);
+  return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+}
+
+// FP64 sums of the real and the imaginary parts of a[0 .. n) in an order
+// that does not depend on the block size (so launch shapes never change
+// results): 16 fixed segments, each summed by one wave with lane l taking
+// every 64th element of the segment, then the segments in order.  `red`
+// holds 32 doubles of LDS; thread 0 receives the sums.
+template <typename T>
+__device__ __forceinline__ void row_sums_fixed_order(const C2<T>* __restrict__ a, int n, double* red, double& s0,
+                                                     double& s1) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int seg = (n + 15) / 16;
+  for (int q = wave; q < 16; q += nw) {
+    const int lo = q * seg, hi = min(lo + seg, n);
+    double p0 = 0.0, p1 = 0.0;
+    for (int x = lo + lane; x < hi; x += 64) {
+      p0 += (double)a[x].re;
+      p1 += (double)a[x].im;
+    }
+    p0 = wave_sum(p0);
+    p1 = wave_sum(p1);
+    if (lane == 0) {
+      red[q] = p0;
+      red[16 + q] = p1;
+    }
+  }
+  __syncthreads();
+  s0 = 0.0;
+  s1 = 0.0;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 16; ++q) {
+      s0 += red[q];
+      s1 += red[16 + q];
+    }
+  }
 }
 
 // ------------------------------------------- forward transform (with gather)
@@ -327,29 +377,29 @@ __device__ __forceinline__ void forward_body(const Consts& c, const T* __restric
   double* red = reinterpret_cast<double*>(b);  // idle until the transform
   const int j0 = 2 * bx, j1 = j0 + 1;
   const bool has1 = j1 < c.ny;
-  double s0 = 0.0, s1 = 0.0;
-#pragma unroll 4
-  for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
-    T v[2] = {T(0), T(0)};
-    for (int q = 0; q < (has1 ? 2 : 1); ++q) {
-      const int j = j0 + q;
-      if (MODE == 2) {
-        v[q] = T(drc_field[(size_t)j * c.nx + x]);
-      } else {
-        T g[9];
-        if (MODE == 0)
-          pull_g<T>(c, G, rows, x, j, g);
-        else
-          local_pop<T>(c, G, x, j, g);
-        v[q] = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+  const int j1c = has1 ? j1 : j0;  // a missing second row re-reads the first; dropped below
+  // U columns per thread per round: every load of a round is issued before
+  // the first sum (the column index is clamped, the stores are guarded)
+  constexpr int U = 4;
+  for (int x0 = threadIdx.x; x0 < c.nx; x0 += U * blockDim.x) {
+    T v0[U], v1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = min(x0 + u * (int)blockDim.x, c.nx - 1);
+      v0[u] = charge_at<T, MODE>(c, G, rows, drc_field, x, j0);
+      v1[u] = charge_at<T, MODE>(c, G, rows, drc_field, x, j1c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = x0 + u * (int)blockDim.x;
+      if (x < c.nx) {
+        a[x] = C2<T>{v0[u], has1 ? v1[u] : T(0)};
       }
     }
-    a[x] = C2<T>{v[0], v[1]};
-    s0 += (double)v[0];
-    s1 += (double)v[1];
   }
-  s0 = block_sum(s0, red);
-  s1 = block_sum(s1, red + 16);
+  __syncthreads();
+  double s0, s1;
+  row_sums_fixed_order<T>(a, c.nx, red, s0, s1);
   if (threadIdx.x == 0) {
     dcsum[j0] = s0;
     if (has1) dcsum[j1] = s1;
@@ -372,7 +422,7 @@ __device__ __forceinline__ void forward_body(const Consts& c, const T* __restric
 }
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
+__global__ void __launch_bounds__(1024) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
                                                  const double* __restrict__ drc_field, FftPlan pl,
                                                  const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
                                                  double* __restrict__ dcsum) {
@@ -558,32 +608,47 @@ __device__ __forceinline__ void tri_reduced_body(const Consts& c, const T* __res
   // the first chunk has no lower response; the last one no upper response
   const T we_first = ttab(tt, c.MP, CH_FIRST, 2, kChunk - 1, m);
   const T vs_last = ttab(tt, c.MP, CH_LAST, 1, 0, m);
-#pragma unroll 8
-  for (int k = 0; k < nc - 1; ++k) {
-    const T ve = k == 0 ? T(0) : ve_in;
-    const T we = k == 0 ? we_first : we_in;
-    const T vs = k + 1 == nc - 1 ? vs_last : vs_in;
-    const T ws = k + 1 == nc - 1 ? T(0) : ws_in;
-    const C2<T> ye = ends[(2 * (size_t)k + 1) * MP + m];
-    const C2<T> ys = ends[(2 * (size_t)(k + 1)) * MP + m];
-    const T beta = -we + ve * g01_prev;
-    const T gamma = -vs;
-    const T inv = T(1) / (T(1) - beta * gamma);
-    const C2<T> D0 = {ye.re + ve * h0_prev.re, ye.im + ve * h0_prev.im};
-    const C2<T> D1 = ys;
-    const C2<T> H0 = {(D0.re - beta * D1.re) * inv, (D0.im - beta * D1.im) * inv};
-    const C2<T> H1 = {(D1.re - gamma * D0.re) * inv, (D1.im - gamma * D0.im) * inv};
-    const T g01 = beta * ws * inv;
-    const T g11 = -ws * inv;
-    T* q = gh + (6 * (size_t)k) * MP + m;
-    q[0] = g01;
-    q[MP] = g11;
-    q[2 * MP] = H0.re;
-    q[3 * MP] = H0.im;
-    q[4 * MP] = H1.re;
-    q[5 * MP] = H1.im;
-    g01_prev = g01;
-    h0_prev = H0;
+  // interfaces in rounds of KB: the loads of a round are issued first (the
+  // elimination itself is a serial chain over k)
+  constexpr int KB = 8;
+  for (int k0 = 0; k0 < nc - 1; k0 += KB) {
+    C2<T> yev[KB], ysv[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = min(k0 + u, nc - 2);
+      yev[u] = ends[(2 * (size_t)k + 1) * MP + m];
+      ysv[u] = ends[(2 * (size_t)(k + 1)) * MP + m];
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = k0 + u;
+      if (k < nc - 1) {
+        const T ve = k == 0 ? T(0) : ve_in;
+        const T we = k == 0 ? we_first : we_in;
+        const T vs = k + 1 == nc - 1 ? vs_last : vs_in;
+        const T ws = k + 1 == nc - 1 ? T(0) : ws_in;
+        const C2<T> ye = yev[u];
+        const C2<T> ys = ysv[u];
+        const T beta = -we + ve * g01_prev;
+        const T gamma = -vs;
+        const T inv = T(1) / (T(1) - beta * gamma);
+        const C2<T> D0 = {ye.re + ve * h0_prev.re, ye.im + ve * h0_prev.im};
+        const C2<T> D1 = ys;
+        const C2<T> H0 = {(D0.re - beta * D1.re) * inv, (D0.im - beta * D1.im) * inv};
+        const C2<T> H1 = {(D1.re - gamma * D0.re) * inv, (D1.im - gamma * D0.im) * inv};
+        const T g01 = beta * ws * inv;
+        const T g11 = -ws * inv;
+        T* q = gh + (6 * (size_t)k) * MP + m;
+        q[0] = g01;
+        q[MP] = g11;
+        q[2 * MP] = H0.re;
+        q[3 * MP] = H0.im;
+        q[4 * MP] = H1.re;
+        q[5 * MP] = H1.im;
+        g01_prev = g01;
+        h0_prev = H0;
+      }
+    }
   }
   C2<T> bnext = {T(0), T(0)};
 #pragma unroll 8
@@ -604,30 +669,66 @@ __global__ void __launch_bounds__(64) k_tri_reduced(Consts c, const T* __restric
   tri_reduced_body<T>(c, tt, ends, gh, iface, blockIdx.x);
 }
 
-// Solution of row j, wavenumber m: the chunk-local y (in spec) plus the
-// responses to the interface values.
-template <typename T>
-__device__ __forceinline__ C2<T> solved_mode(const Consts& c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
-                                             const C2<T>* __restrict__ iface, int j, int m) {
-  C2<T> y = spec[(size_t)j * c.MP + m];
-  if (c.NC > 1) {
-    const int k = j / kChunk, i = j - k * kChunk;
-    const int type = chunk_type(k, c.NC);
-    const size_t MP = c.MP;
-    if (k > 0) {
-      const T v = ttab(tt, c.MP, type, 1, i, m);
-      const C2<T> L = iface[(2 * (size_t)(k - 1)) * MP + m];
-      y.re += v * L.re;
-      y.im += v * L.im;
+// Solved spectra of a row pair in LDS: the chunk-local y (in spec) plus the
+// responses v, w to the interface values L (below the chunk) and R (above
+// it).  Both rows of a pair lie in one chunk (kChunk is even), so the
+// presence of L and R is uniform over the block and is resolved by the
+// template outside the loop; the loads of a round carry no branches.
+template <typename T, bool HL, bool HR>
+__device__ __forceinline__ void inverse_gather(const Consts& c, const C2<T>* __restrict__ spec,
+                                               const T* __restrict__ tt, const C2<T>* __restrict__ iface,
+                                               int j0, bool has1, int N, C2<T>* __restrict__ a) {
+  const size_t MP = c.MP;
+  const int k = j0 / kChunk, i0 = j0 - k * kChunk;
+  const int type = chunk_type(k, c.NC);
+  const C2<T>* y0 = spec + (size_t)j0 * MP;
+  const C2<T>* y1 = spec + (size_t)(has1 ? j0 + 1 : j0) * MP;
+  const T* v0 = tt + ((size_t)(type * 3 + 1) * kChunk + i0) * MP;
+  const T* w0 = tt + ((size_t)(type * 3 + 2) * kChunk + i0) * MP;
+  const int i1 = has1 ? i0 + 1 : i0;
+  const T* v1 = tt + ((size_t)(type * 3 + 1) * kChunk + i1) * MP;
+  const T* w1 = tt + ((size_t)(type * 3 + 2) * kChunk + i1) * MP;
+  const C2<T>* Lp = iface + (2 * (size_t)(HL ? k - 1 : 0)) * MP;
+  const C2<T>* Rp = iface + (2 * (size_t)k + 1) * MP;
+  constexpr int U = 4;
+  for (int m0 = threadIdx.x; m0 < N; m0 += U * blockDim.x) {
+    C2<T> X[U], Y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = min(m0 + u * (int)blockDim.x, N - 1);
+      const int mm = m < c.M ? m : N - m;
+      X[u] = y0[mm];
+      Y[u] = y1[mm];
+      if (HL) {
+        const C2<T> L = Lp[mm];
+        const T a0 = v0[mm], a1 = v1[mm];
+        X[u].re += a0 * L.re;
+        X[u].im += a0 * L.im;
+        Y[u].re += a1 * L.re;
+        Y[u].im += a1 * L.im;
+      }
+      if (HR) {
+        const C2<T> R = Rp[mm];
+        const T b0 = w0[mm], b1 = w1[mm];
+        X[u].re += b0 * R.re;
+        X[u].im += b0 * R.im;
+        Y[u].re += b1 * R.re;
+        Y[u].im += b1 * R.im;
+      }
     }
-    if (k < c.NC - 1) {
-      const T w = ttab(tt, c.MP, type, 2, i, m);
-      const C2<T> R = iface[(2 * (size_t)k + 1) * MP + m];
-      y.re += w * R.re;
-      y.im += w * R.im;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = m0 + u * (int)blockDim.x;
+      if (m < N) {
+        C2<T> x = X[u], y = has1 ? Y[u] : C2<T>{T(0), T(0)};
+        if (m >= c.M) {  // upper half: conjugates of the lower one
+          x.im = -x.im;
+          y.im = -y.im;
+        }
+        a[m] = m == 0 ? C2<T>{T(0), T(0)} : C2<T>{x.re - y.im, x.im + y.re};
+      }
     }
   }
-  return y;
 }
 
 // --------------------------------------------------- inverse transform
@@ -645,22 +746,16 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
   const int j0 = 2 * bx, j1 = j0 + 1;
   const bool has1 = j1 < c.ny;
   const int N = pl.n;
-#pragma unroll 4
-  for (int m = threadIdx.x; m < N; m += blockDim.x) {
-    C2<T> Z = {T(0), T(0)};
-    if (m > 0) {
-      const bool lowh = m < c.M;
-      const int mm = lowh ? m : N - m;
-      C2<T> X = solved_mode<T>(c, spec, tt, iface, j0, mm);
-      C2<T> Y = has1 ? solved_mode<T>(c, spec, tt, iface, j1, mm) : C2<T>{T(0), T(0)};
-      if (!lowh) {
-        X.im = -X.im;
-        Y.im = -Y.im;
-      }
-      Z = C2<T>{X.re - Y.im, X.im + Y.re};
-    }
-    a[m] = Z;
-  }
+  const int k = j0 / kChunk;
+  const bool hl = c.NC > 1 && k > 0, hr = c.NC > 1 && k < c.NC - 1;
+  if (hl && hr)
+    inverse_gather<T, true, true>(c, spec, tt, iface, j0, has1, N, a);
+  else if (hl)
+    inverse_gather<T, true, false>(c, spec, tt, iface, j0, has1, N, a);
+  else if (hr)
+    inverse_gather<T, false, true>(c, spec, tt, iface, j0, has1, N, a);
+  else
+    inverse_gather<T, false, false>(c, spec, tt, iface, j0, has1, N, a);
   __syncthreads();
   C2<T>* z = fft_lds<T, true>(a, b, pl, tw);
   const T inv = T(1.0 / (double)N);
@@ -671,7 +766,7 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
+__global__ void __launch_bounds__(1024) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
                                                  const C2<T>* __restrict__ iface, FftPlan pl,
                                                  const C2<T>* __restrict__ tw, T* __restrict__ phi) {
   inverse_body<T>(c, spec, tt, iface, pl, tw, phi, blockIdx.x);
@@ -997,7 +1092,7 @@ __device__ __forceinline__ bool slot_emits(const SlotDesc& d) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) kb_forward(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+__global__ void __launch_bounds__(1024) kb_forward(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
@@ -1034,7 +1129,7 @@ __global__ void __launch_bounds__(64) kb_tri_reduced(const SlotDesc* __restrict_
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) kb_inverse(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+__global__ void __launch_bounds__(1024) kb_inverse(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
