@@ -79,9 +79,9 @@ ec::FftPlan make_plan(int n) {
 }
 
 struct Layout {
-  int P, M, MP, NC;
+  int P, M, MP, NC, KP;
   size_t tsize;
-  size_t off_f[2], off_g[2], off_phi, off_spec, off_tt, off_ends, off_gh, off_iface, off_tw, off_rows,
+  size_t off_f[2], off_g[2], off_phi, off_spec, off_tt, off_ends, off_gh, off_rf, off_iface, off_tw, off_rows,
       off_rowsd, off_dmean, off_mom, off_stats, total;
 };
 
@@ -93,6 +93,7 @@ Layout make_layout(const lbm_ec_params& p) {
   L.M = p.nx / 2 + 1;
   L.MP = (L.M + elems - 1) / elems * elems;
   L.NC = (p.ny + ec::kChunk - 1) / ec::kChunk;
+  L.KP = L.NC >= 2 ? (L.NC - 1 + 7) / 8 * 8 : 0;
   const size_t ny = (size_t)p.ny, nx = (size_t)p.nx, nc = (size_t)L.NC;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -110,6 +111,7 @@ Layout make_layout(const lbm_ec_params& p) {
   L.off_tt = take(4 * 3 * (size_t)ec::kChunk * L.MP * L.tsize);
   L.off_ends = take(nc * 2 * L.MP * 2 * L.tsize);
   L.off_gh = take(nc * 6 * L.MP * L.tsize);
+  L.off_rf = take((size_t)L.MP * ec::RF_COUNT * L.KP * L.tsize);
   L.off_iface = take(nc * 2 * L.MP * 2 * L.tsize);
   L.off_tw = take(nx * 2 * L.tsize);
   L.off_rows = take(ec::ROW_COUNT * ny * L.tsize);
@@ -202,6 +204,7 @@ int setup(lbm_ec* h, unsigned char* ws) {
   c.M = L.M;
   c.MP = L.MP;
   c.NC = L.NC;
+  c.KP = L.KP;
   c.wp = 1.0 / p.tau_plus;
   c.wm = 1.0 / tau_m;
   c.wgp = 1.0 / tau_gp;
@@ -274,6 +277,9 @@ int setup(lbm_ec* h, unsigned char* ws) {
   const int KC = ec::kChunk;
   std::vector<T> tt((size_t)4 * 3 * KC * MP, T(0));
   auto tidx = [&](int type, int q, int i, int m) { return ((size_t)(type * 3 + q) * KC + i) * MP + m; };
+  // end entries of the responses that couple neighbouring chunks (FP64)
+  std::vector<double> ve_in(M, 0.0), we_in(M, 0.0), vs_in(M, 0.0), ws_in(M, 0.0), we_first(M, 0.0),
+      vs_last(M, 0.0);
   for (int type = 0; type < 4; ++type) {
     int len;
     if (type == ec::CH_SINGLE) {
@@ -306,6 +312,41 @@ int setup(lbm_ec* h, unsigned char* ws) {
         x[len - 1] = dp[len - 1];
         for (int i = len - 2; i >= 0; --i) x[i] = dp[i] - cpv[i] * x[i + 1];
         for (int i = 0; i < len; ++i) tt[tidx(type, q, i, m)] = (T)x[i];
+        if (type == ec::CH_INTERIOR) {
+          (q == 1 ? ve_in : we_in)[m] = x[len - 1];
+          (q == 1 ? vs_in : ws_in)[m] = x[0];
+        }
+        if (type == ec::CH_FIRST && q == 2) we_first[m] = x[len - 1];
+        if (type == ec::CH_LAST && q == 1) vs_last[m] = x[0];
+      }
+    }
+  }
+  // factors of the interface system (its matrix is fixed): the block
+  // elimination over interfaces k = 0 .. NC-2 with 2x2 pivots, in FP64, as
+  // the per-(m, k) coefficients of the two recurrences the device runs
+  std::vector<T> rf((size_t)MP * ec::RF_COUNT * L.KP, T(0));
+  if (NC >= 2) {
+    const int K = NC - 1, KP = L.KP;
+    for (int m = 1; m < M; ++m) {
+      double g01_prev = 0.0;
+      T* f = rf.data() + (size_t)m * ec::RF_COUNT * KP;
+      for (int k = 0; k < K; ++k) {
+        const double ve = k == 0 ? 0.0 : ve_in[m];
+        const double we = k == 0 ? we_first[m] : we_in[m];
+        const double vs = k + 1 == K ? vs_last[m] : vs_in[m];
+        const double wsk = k + 1 == K ? 0.0 : ws_in[m];
+        const double beta = -we + ve * g01_prev;
+        const double gamma = -vs;
+        const double inv = 1.0 / (1.0 - beta * gamma);
+        const double g01 = beta * wsk * inv;
+        f[ec::RF_INV * KP + k] = (T)inv;
+        f[ec::RF_IB * KP + k] = (T)(inv * beta);
+        f[ec::RF_A * KP + k] = (T)(inv * ve);
+        f[ec::RF_P * KP + k] = (T)(inv * vs);
+        f[ec::RF_Q * KP + k] = (T)(inv * vs * ve);
+        f[ec::RF_C * KP + k] = (T)(wsk * inv);
+        f[ec::RF_G * KP + k] = (T)g01;
+        g01_prev = g01;
       }
     }
   }
@@ -319,6 +360,8 @@ int setup(lbm_ec* h, unsigned char* ws) {
   EC_HIP(hipMemcpyAsync(h->b.rows, rows.data(), rows.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.rowsd, rowsd.data(), rowsd.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.tt, tt.data(), tt.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
+  if (!rf.empty())
+    EC_HIP(hipMemcpyAsync(h->b.rf, rf.data(), rf.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemsetAsync(h->b.iface, 0, (size_t)NC * 2 * MP * 2 * sizeof(T), h->s));
   EC_HIP(hipMemcpyAsync(h->b.tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemsetAsync(ws + L.off_spec, 0, (size_t)ny * MP * 2 * sizeof(T), h->s));
@@ -408,6 +451,7 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
   h->b.tt = ws + L.off_tt;
   h->b.ends = ws + L.off_ends;
   h->b.gh = ws + L.off_gh;
+  h->b.rf = ws + L.off_rf;
   h->b.iface = ws + L.off_iface;
   h->b.tw = ws + L.off_tw;
   h->b.rows = ws + L.off_rows;
@@ -888,6 +932,7 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
   h->b.tt = ws + L.off_tt;
   h->b.ends = ws + L.off_ends;
   h->b.gh = ws + L.off_gh;
+  h->b.rf = ws + L.off_rf;
   h->b.iface = ws + L.off_iface;
   h->b.tw = ws + L.off_tw;
   h->b.rows = ws + L.off_rows;

@@ -31,6 +31,7 @@ struct Consts {
   int M;       // number of non-negative x wavenumbers, nx/2 + 1
   int MP;      // row pitch of spectral arrays, elements
   int NC;      // number of y chunks, ceil(ny / kChunk)
+  int KP;      // row pitch of the interface factor table (NC - 1 rounded up to 8)
   double wp, wm, wgp, wgm;  // TRT rates: fluid +/-, charge +/-
   double K;                 // ion mobility
   double eps;               // permittivity
@@ -53,6 +54,15 @@ struct Consts {
   double noise_amp;
   uint64_t seed;
 };
+
+// The interface system of the y solves is solved by recursive doubling (one
+// wave per wavenumber, kScanPerLane interfaces per lane) when it has at most
+// kScanMax interfaces, and by a serial block elimination otherwise.
+constexpr int kScanPerLane = 8;
+constexpr int kScanMax = 64 * kScanPerLane;
+
+// Factors of the interface system per (m, k), in this order (table rf).
+enum ReducedFactor { RF_INV = 0, RF_IB, RF_A, RF_P, RF_Q, RF_C, RF_G, RF_COUNT };
 
 // Per-row tables in the storage type (index k * ny + j).
 enum RowTable {
@@ -86,6 +96,7 @@ struct Bufs {
   void* tt;      // [4 types][3: cp, v, w][kChunk][MP] chunk tables of the y solves
   void* ends;    // [P][2][MP] complex: first / last row of each chunk's local solution
   void* gh;      // [P][6][MP]: block-elimination scratch of the interface system
+  void* rf;      // [MP][7][KP]: data-independent factors of the interface system
   void* iface;   // [P][2][MP] complex: interface values a_k (last row of chunk k),
                  //                      b_k (first row of chunk k+1)
   void* tw;      // [nx] complex twiddles exp(-2 pi i k / nx)

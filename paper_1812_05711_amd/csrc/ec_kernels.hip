@@ -669,6 +669,124 @@ __global__ void __launch_bounds__(64) k_tri_reduced(Consts c, const T* __restric
   tri_reduced_body<T>(c, tt, ends, gh, iface, blockIdx.x);
 }
 
+// The interface system by recursive doubling, one wave per wavenumber m.
+// Its matrix does not depend on the data, so the block elimination above
+// reduces, with factors precomputed per (m, k) (table rf), to two first-order
+// linear recurrences over the interfaces:
+//   h_k = A_k h_{k-1} + B_k,         B_k = inv_k ye_k - ib_k ys_k   (h = H0)
+//   b_k = C_k b_{k+1} + H1_k,        H1_k = inv_k ys_k + P_k ye_k + Q_k h_{k-1}
+//   a_k = h_k - g_k b_{k+1}
+// (h_{-1} = 0, b_{NC-1} = 0).  Lane l holds interfaces l E .. l E + E - 1
+// (E = kScanPerLane); each recurrence composes the affine maps of a lane,
+// scans the composed maps across the 64 lanes (Hillis-Steele with shuffles)
+// and re-runs the lane's own elements from the value that enters it.
+template <typename T>
+__device__ __forceinline__ C2<T> shfl_up_c(C2<T> v, int d) {
+  return C2<T>{__shfl_up(v.re, d, 64), __shfl_up(v.im, d, 64)};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> shfl_down_c(C2<T> v, int d) {
+  return C2<T>{__shfl_down(v.re, d, 64), __shfl_down(v.im, d, 64)};
+}
+
+template <typename T>
+__device__ __forceinline__ void tri_scan_body(const Consts& c, const T* __restrict__ rf,
+                                              const C2<T>* __restrict__ ends, C2<T>* __restrict__ iface, int m) {
+  constexpr int E = kScanPerLane;
+  const int lane = threadIdx.x & 63;
+  const int K = c.NC - 1;
+  const size_t MP = c.MP;
+  const T* f = rf + (size_t)m * RF_COUNT * c.KP;
+  const int k0 = lane * E;
+  C2<T> ye[E], ys[E], H0[E], H1[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = min(k0 + e, K - 1);
+    ye[e] = ends[(2 * (size_t)k + 1) * MP + m];
+    ys[e] = ends[(2 * (size_t)(k + 1)) * MP + m];
+  }
+  // forward: compose this lane's maps h -> A h + B
+  T Al = T(1);
+  C2<T> Bl = {T(0), T(0)};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = k0 + e;
+    if (k < K) {
+      const T inv = f[RF_INV * c.KP + k], ib = f[RF_IB * c.KP + k], A = f[RF_A * c.KP + k];
+      const C2<T> B = {inv * ye[e].re - ib * ys[e].re, inv * ye[e].im - ib * ys[e].im};
+      Bl = C2<T>{A * Bl.re + B.re, A * Bl.im + B.im};
+      Al = A * Al;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T Ao = __shfl_up(Al, d, 64);
+    const C2<T> Bo = shfl_up_c(Bl, d);
+    if (lane >= d) {
+      Bl = C2<T>{Al * Bo.re + Bl.re, Al * Bo.im + Bl.im};
+      Al = Al * Ao;
+    }
+  }
+  C2<T> hp = shfl_up_c(Bl, 1);  // h entering this lane (h_{-1} = 0)
+  if (lane == 0) hp = C2<T>{T(0), T(0)};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = k0 + e;
+    if (k < K) {
+      const T inv = f[RF_INV * c.KP + k], ib = f[RF_IB * c.KP + k], A = f[RF_A * c.KP + k];
+      const T P = f[RF_P * c.KP + k], Q = f[RF_Q * c.KP + k];
+      H1[e] = C2<T>{inv * ys[e].re + P * ye[e].re + Q * hp.re, inv * ys[e].im + P * ye[e].im + Q * hp.im};
+      const C2<T> B = {inv * ye[e].re - ib * ys[e].re, inv * ye[e].im - ib * ys[e].im};
+      hp = C2<T>{A * hp.re + B.re, A * hp.im + B.im};
+      H0[e] = hp;
+    }
+  }
+  // backward: compose b_next -> C b_next + H1 over this lane's elements
+  T Cl = T(1);
+  C2<T> Dl = {T(0), T(0)};
+#pragma unroll
+  for (int e = E - 1; e >= 0; --e) {
+    const int k = k0 + e;
+    if (k < K) {
+      const T C = f[RF_C * c.KP + k];
+      Dl = C2<T>{C * Dl.re + H1[e].re, C * Dl.im + H1[e].im};
+      Cl = C * Cl;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T Co = __shfl_down(Cl, d, 64);
+    const C2<T> Do = shfl_down_c(Dl, d);
+    if (lane + d < 64) {
+      Dl = C2<T>{Cl * Do.re + Dl.re, Cl * Do.im + Dl.im};
+      Cl = Cl * Co;
+    }
+  }
+  C2<T> bn = shfl_down_c(Dl, 1);  // b leaving this lane upwards (b_{NC-1} = 0)
+  if (lane == 63) bn = C2<T>{T(0), T(0)};
+#pragma unroll
+  for (int e = E - 1; e >= 0; --e) {
+    const int k = k0 + e;
+    if (k < K) {
+      const T C = f[RF_C * c.KP + k], g = f[RF_G * c.KP + k];
+      const C2<T> a = {H0[e].re - g * bn.re, H0[e].im - g * bn.im};
+      const C2<T> b = {H1[e].re + C * bn.re, H1[e].im + C * bn.im};
+      iface[(2 * (size_t)k) * MP + m] = a;
+      iface[(2 * (size_t)k + 1) * MP + m] = b;
+      bn = b;
+    }
+  }
+}
+
+// Four wavenumbers per 256-thread block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_tri_scan(Consts c, const T* __restrict__ rf, const C2<T>* __restrict__ ends,
+                                                  C2<T>* __restrict__ iface) {
+  const int m = 1 + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (m >= c.M) return;
+  tri_scan_body<T>(c, rf, ends, iface, m);
+}
+
 // Solved spectra of a row pair in LDS: the chunk-local y (in spec) plus the
 // responses v, w to the interface values L (below the chunk) and R (above
 // it).  Both rows of a pair lie in one chunk (kChunk is even), so the
@@ -1118,14 +1236,22 @@ __global__ void __launch_bounds__(64) kb_tri_local(const SlotDesc* __restrict__ 
   tri_local_body<T>(d.c, (const T*)d.b.tt, (C2<T>*)d.b.spec, (C2<T>*)d.b.ends, lb % nbx, lb / nbx);
 }
 
+// 256 threads per block: four wavenumbers per block on the scan path, 256 on
+// the serial one (chosen per slot by its interface count).
 template <typename T>
-__global__ void __launch_bounds__(64) kb_tri_reduced(const SlotDesc* __restrict__ D, const int* __restrict__ off,
-                                                     int ns) {
+__global__ void __launch_bounds__(256) kb_tri_reduced(const SlotDesc* __restrict__ D, const int* __restrict__ off,
+                                                      int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
-  tri_reduced_body<T>(d.c, (const T*)d.b.tt, (const C2<T>*)d.b.ends, (T*)d.b.gh, (C2<T>*)d.b.iface,
-                      blockIdx.x - off[s]);
+  const int lb = blockIdx.x - off[s];
+  if (d.c.NC - 1 <= kScanMax) {
+    const int m = 1 + lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (m >= d.c.M) return;
+    tri_scan_body<T>(d.c, (const T*)d.b.rf, (const C2<T>*)d.b.ends, (C2<T>*)d.b.iface, m);
+  } else {
+    tri_reduced_body<T>(d.c, (const T*)d.b.tt, (const C2<T>*)d.b.ends, (T*)d.b.gh, (C2<T>*)d.b.iface, lb);
+  }
 }
 
 template <typename T>
@@ -1208,7 +1334,9 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu) {
     case BK_INVERSE: return (c.ny + 1) / 2;
     case BK_MEAN: return 1;
     case BK_TRI_LOCAL: return nm > 0 ? ((nm + 63) / 64) * c.NC : 0;
-    case BK_TRI_REDUCED: return (nm > 0 && c.NC >= 2) ? (nm + 63) / 64 : 0;
+    case BK_TRI_REDUCED:
+      if (nm <= 0 || c.NC < 2) return 0;
+      return c.NC - 1 <= kScanMax ? (nm + 3) / 4 : (nm + 255) / 256;
     case BK_COLLIDE: return ((c.nx + tu.cbx - 1) / tu.cbx) * ((c.ny + tu.cby - 1) / tu.cby);
     case BK_STATS: return 1;
   }
@@ -1228,7 +1356,7 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
     hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(64), 0, s, d_desc,
                        d_off + BK_TRI_LOCAL * row, ns);
   if (totals[BK_TRI_REDUCED])
-    hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(64), 0, s, d_desc,
+    hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(256), 0, s, d_desc,
                        d_off + BK_TRI_REDUCED * row, ns);
   if (totals[BK_INVERSE])
     hipLaunchKernelGGL(kb_inverse<T>, dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s, d_desc, d_off + BK_INVERSE * row, ns);
@@ -1302,8 +1430,12 @@ hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
                      (C2<T>*)b.spec, (C2<T>*)b.ends);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || c.NC < 2) return e;
-  hipLaunchKernelGGL(k_tri_reduced<T>, dim3((nm + 63) / 64), dim3(64), 0, s, c, (const T*)b.tt,
-                     (const C2<T>*)b.ends, (T*)b.gh, (C2<T>*)b.iface);
+  if (c.NC - 1 <= kScanMax)
+    hipLaunchKernelGGL(k_tri_scan<T>, dim3((nm + 3) / 4), dim3(256), 0, s, c, (const T*)b.rf,
+                       (const C2<T>*)b.ends, (C2<T>*)b.iface);
+  else
+    hipLaunchKernelGGL(k_tri_reduced<T>, dim3((nm + 63) / 64), dim3(64), 0, s, c, (const T*)b.tt,
+                       (const C2<T>*)b.ends, (T*)b.gh, (C2<T>*)b.iface);
   return hipGetLastError();
 }
 

@@ -1,0 +1,49 @@
+"""Parity of the Poisson chain alone (x transforms, per-wavenumber y solves
+on both interface-solve paths, the x-mean mode) with the oracle's solve,
+through lbm_ec_poisson, on seeded charge fields.
+
+The y systems split into chunks of 32 rows; the cases give interface
+systems of 0 (one chunk), 1, 26, 127 and 512 interfaces (recursive
+doubling, 512 is its largest size) and 514 (serial block elimination).
+Tolerances: FP64 1e-11 relative to max |phi|; FP32 storage 1e-6 (the
+m >= 1 modes in FP32 arithmetic, the mean mode in FP64).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import Params
+from oracle.lattice import lattice_constants
+from oracle.poisson import solve
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(T=200.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6, noise_amp=1e-3,
+            seed=181205711)
+CASES = [(16, 20), (24, 40), (40, 840), (8, 4096), (6, 16416), (6, 16480)]
+TOL = {"fp64": 1e-11, "fp32_f64math": 1e-6, "fp32": 1e-6}
+
+
+def _charge(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    y = (np.arange(ny) + 0.5) / ny
+    return (np.exp(-3.0 * y)[:, None] * (1.0 + 0.3 * rng.standard_normal((ny, nx)))).astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_f64math", "fp32"])
+@pytest.mark.parametrize("nx,ny", CASES)
+def test_poisson_matches_oracle(nx, ny, precision):
+    import torch
+
+    from paper_1812_05711_amd.lbm_ec import Simulation
+
+    kw = dict(BASE, nx=nx, ny=ny)
+    rho_nd = _charge(nx, ny, 7 + nx + ny)
+    eps = lattice_constants(Params(**kw)).eps
+    phi_o = solve(rho_nd * eps / float(ny) ** 2, eps)
+    sim = Simulation(device="cuda:0", precision=precision, **kw)
+    phi_g = sim.poisson(torch.from_numpy(rho_nd)).cpu().numpy()
+    sim.close()
+    err = np.abs(phi_g - phi_o).max() / np.abs(phi_o).max()
+    print(nx, ny, precision, f"{err:.2e}", flush=True)
+    assert err <= TOL[precision], err
