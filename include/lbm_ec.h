@@ -166,14 +166,14 @@ int lbm_ec_stats(lbm_ec_t* h, double* out);
  * lbm_ec_profile_end stops, waits for the last event and returns, per kernel
  * class, the summed elapsed milliseconds and the launch count in ms[k] and
  * launches[k] for k < n.  Classes: 0 forward transform (with the charge
- * gather), 1 x-mean mode, 2 per-wavenumber solves, 3 inverse transform,
- * 4 collide-stream.  The events are created on first use and kept by the
+ * gather), 1 y solves (the x-mean mode and the per-wavenumber systems),
+ * 2 inverse transform, 3 collide-stream.  The events are created on first use and kept by the
  * handle (host-side driver objects, no device memory). */
 int lbm_ec_profile_begin(lbm_ec_t* h);
 int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 
 /* Launch shapes, which never change results: threads per x-transform block
- * (64, 128, 256, 512 or 1024) and the collide block shape (collide_bx x collide_by
+ * (64, 128, 256 or 512) and the collide block shape (collide_bx x collide_by
  * threads, product 64, 128 or 256).  Defaults 256 and 64 x 4.  Applies to the
  * following steps; EINVAL for other values.  The autotuner in
  * paper_1812_05711_amd/autotune.py picks them by timing. */

@@ -10,7 +10,7 @@ import hashlib
 import json
 import os
 
-FFT_THREADS = (128, 256, 512, 1024)
+FFT_THREADS = (128, 256, 512)
 COLLIDE_SHAPES = ((64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (256, 1), (32, 4), (32, 8))
 DEFAULT = (256, 64, 4)
 

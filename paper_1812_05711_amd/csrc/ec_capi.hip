@@ -90,6 +90,10 @@ Layout make_layout(const lbm_ec_params& p) {
   L.tsize = p.precision == LBM_EC_FP64 ? 8 : 4;
   const int elems = (int)(256 / L.tsize);  // pitch multiple of 256 bytes
   L.P = (p.nx + elems - 1) / elems * elems;
+  // a row pitch that is a multiple of 4 KiB is padded by 256 bytes, so that
+  // the rows and the population planes a block streams from together do not
+  // sit at power-of-two distances (which map them onto the same channels)
+  if ((L.P * L.tsize) % 4096 == 0) L.P += elems;
   L.M = p.nx / 2 + 1;
   L.MP = (L.M + elems - 1) / elems * elems;
   L.NC = (p.ny + ec::kChunk - 1) / ec::kChunk;
@@ -148,7 +152,7 @@ int validate(const lbm_ec_params* p) {
 }  // namespace
 
 // Kernel classes timed by the profiling hooks.
-enum { KC_FORWARD = 0, KC_MEAN, KC_TRIDIAG, KC_INVERSE, KC_COLLIDE, KC_COUNT };
+enum { KC_FORWARD = 0, KC_TRIDIAG, KC_INVERSE, KC_COLLIDE, KC_COUNT };
 
 struct Profiler {
   bool on = false;
@@ -398,7 +402,6 @@ int prof_mark(lbm_ec* h, int cls) {
 template <typename T>
 int poisson_chain(lbm_ec* h, int mode, int src) {
   EC_TIMED(h, KC_FORWARD, (ec::launch_forward<T>(h->c, h->b, h->plan, mode, src, h->tu, h->s)));
-  EC_TIMED(h, KC_MEAN, (ec::launch_mean_mode<T>(h->c, h->b, h->s)));
   EC_TIMED(h, KC_TRIDIAG, (ec::launch_tridiag<T>(h->c, h->b, h->s)));
   EC_TIMED(h, KC_INVERSE, (ec::launch_inverse<T>(h->c, h->b, h->plan, h->tu, h->s)));
   return LBM_EC_OK;
@@ -633,7 +636,8 @@ int rebuild(lbm_ec_batch* B) {
     d.steps_done = sl.inst.steps;
     d.steps_target = sl.target;
     d.hist = sl.hist;
-    const size_t lds = sl.inst.fp32 ? ec::fft_lds_bytes<float>(sl.inst.p.nx) : ec::fft_lds_bytes<double>(sl.inst.p.nx);
+    const size_t lds = sl.inst.fp32 ? ec::fft_lds_bytes<float>(sl.inst.plan, B->tu.fft_threads)
+                                    : ec::fft_lds_bytes<double>(sl.inst.plan, B->tu.fft_threads);
     B->lds = std::max(B->lds, lds);
     for (int k = 0; k < ec::BK_COUNT; ++k) {
       off[(size_t)k * (ns + 1) + q] = B->totals[k];
@@ -847,8 +851,8 @@ void lbm_ec_batch_destroy(lbm_ec_batch_t* B) {
 }
 
 static int check_tuning(int32_t fft_threads, int32_t bx, int32_t by) {
-  if (fft_threads != 64 && fft_threads != 128 && fft_threads != 256 && fft_threads != 512 && fft_threads != 1024)
-    return fail(LBM_EC_EINVAL, "fft_threads must be 64, 128, 256, 512 or 1024");
+  if (fft_threads != 64 && fft_threads != 128 && fft_threads != 256 && fft_threads != 512)
+    return fail(LBM_EC_EINVAL, "fft_threads must be 64, 128, 256 or 512");
   const int t = bx * by;
   if (bx < 1 || by < 1 || (t != 64 && t != 128 && t != 256))
     return fail(LBM_EC_EINVAL, "collide block bx * by must be 64, 128 or 256");

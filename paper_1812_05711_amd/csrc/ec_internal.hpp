@@ -17,6 +17,19 @@ struct FftPlan {
   int r[kMaxRadices];
 };
 
+// The x transforms run in place in one LDS buffer (each pass reads its inputs
+// into registers, the block synchronises, the outputs overwrite the buffer)
+// when every radix has a register butterfly and a pass gives each thread at
+// most kFftPerThread elements; otherwise they ping-pong between two buffers.
+constexpr int kFftPerThread = 16;
+__host__ __device__ inline bool fft_in_place(const FftPlan& pl, int threads) {
+  for (int p = 0; p < pl.nr; ++p) {
+    const int r = pl.r[p];
+    if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return false;
+  }
+  return pl.n <= kFftPerThread * threads;
+}
+
 // Rows per chunk of the partitioned per-wavenumber solves.
 constexpr int kChunk = 32;
 // Chunk types: the whole column (one chunk), the first one (lower electrode
@@ -130,7 +143,7 @@ struct Tuning {
 };
 
 // Batched kernels; slot s owns the blocks [off[k][s], off[k][s+1]) of launch k.
-enum BatchKernel { BK_FORWARD = 0, BK_MEAN, BK_TRI_LOCAL, BK_TRI_REDUCED, BK_INVERSE, BK_COLLIDE, BK_STATS, BK_COUNT };
+enum BatchKernel { BK_FORWARD = 0, BK_TRI_LOCAL, BK_TRI_REDUCED, BK_INVERSE, BK_COLLIDE, BK_STATS, BK_COUNT };
 
 // Blocks that kernel k uses for one instance.
 int batch_blocks(const Consts& c, int k, const Tuning& tu);
@@ -153,10 +166,9 @@ hipError_t launch_init_populations(const Consts& c, const Bufs& b, int dst, hipS
 template <typename T>
 hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src,
                           const Tuning& tu, hipStream_t s);
-template <typename T>
-hipError_t launch_mean_mode(const Consts& c, const Bufs& b, hipStream_t s);
-// per-wavenumber y solves, m >= 1: chunk-local solves, then the interface
-// system (the chunk corrections are applied by launch_inverse)
+// the x-mean mode (beside the chunk-local solves of the m >= 1 y systems),
+// then the interface system (the chunk corrections are applied by
+// launch_inverse)
 template <typename T>
 hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s);
 template <typename T>
@@ -173,8 +185,8 @@ hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_
 template <typename T>
 hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s);
 
-// LDS bytes the x transforms need for length n.
+// LDS bytes of the x-transform kernels for plan pl on blocks of `threads`.
 template <typename T>
-size_t fft_lds_bytes(int n);
+size_t fft_lds_bytes(const FftPlan& pl, int threads);
 
 }  // namespace ec

@@ -199,15 +199,83 @@ __device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftPlan& pl, const C2<T>* __
   return src;
 }
 
-// Two complex buffers of n elements; the second one doubles as the 32-double
-// reduction scratch of k_forward (used before the transform starts).
+// In-place pass of radix R (see fft_in_place): every thread holds up to NB
+// butterflies of the pass in registers between the read and the write phase.
+template <typename T, bool INV, int R, int NB>
+__device__ __forceinline__ void stockham_pass_ip(C2<T>* __restrict__ buf, int N, int Ns,
+                                                 const C2<T>* __restrict__ tw) {
+  const int stride = N / R;
+  const int twstep = N / (Ns * R);
+  C2<T> v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int t = threadIdx.x + q * blockDim.x;
+    if (t < stride) {
+      const int k = t % Ns;
+      const int e = k * twstep;
+      v[q][0] = buf[t];
+      int idx = e;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C2<T> w = tw[idx];
+        if (INV) w.im = -w.im;
+        v[q][r] = cmul(buf[t + r * stride], w);
+        idx += e;
+        if (idx >= N) idx -= N;
+      }
+      if constexpr (R == 2) dft2<T, INV>(v[q]);
+      if constexpr (R == 3) dft3<T, INV>(v[q]);
+      if constexpr (R == 4) dft4<T, INV>(v[q][0], v[q][1], v[q][2], v[q][3]);
+      if constexpr (R == 5) dft5<T, INV>(v[q]);
+      if constexpr (R == 8) dft8<T, INV>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int t = threadIdx.x + q * blockDim.x;
+    if (t < stride) {
+      const int k = t % Ns;
+      const int base = (t / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
+    }
+  }
+}
+
+// The same transform as fft_lds, in place in buffer a (requires
+// fft_in_place(pl, blockDim.x)).
+template <typename T, bool INV>
+__device__ C2<T>* fft_lds_ip(C2<T>* a, const FftPlan& pl, const C2<T>* __restrict__ tw) {
+  constexpr int F = kFftPerThread;
+  const int N = pl.n;
+  int Ns = 1;
+  for (int p = 0; p < pl.nr; ++p) {
+    const int R = pl.r[p];
+    switch (R) {
+      case 2: stockham_pass_ip<T, INV, 2, (F + 1) / 2>(a, N, Ns, tw); break;
+      case 3: stockham_pass_ip<T, INV, 3, (F + 2) / 3>(a, N, Ns, tw); break;
+      case 4: stockham_pass_ip<T, INV, 4, (F + 3) / 4>(a, N, Ns, tw); break;
+      case 5: stockham_pass_ip<T, INV, 5, (F + 4) / 5>(a, N, Ns, tw); break;
+      default: stockham_pass_ip<T, INV, 8, (F + 7) / 8>(a, N, Ns, tw); break;
+    }
+    __syncthreads();
+    Ns *= R;
+  }
+  return a;
+}
+
+// In place: one buffer of n elements plus the 32-double reduction scratch of
+// k_forward.  Ping-pong: two buffers, the second one doubling as the scratch
+// (used before the transform starts).
 template <typename T>
-size_t fft_lds_bytes(int n) {
-  const size_t one = (size_t)n * sizeof(C2<T>);
+size_t fft_lds_bytes(const FftPlan& pl, int threads) {
+  const size_t one = (size_t)pl.n * sizeof(C2<T>);
+  if (fft_in_place(pl, threads)) return one + 32 * sizeof(double);
   return one + (one > 32 * sizeof(double) ? one : 32 * sizeof(double));
 }
-template size_t fft_lds_bytes<double>(int);
-template size_t fft_lds_bytes<float>(int);
+template size_t fft_lds_bytes<double>(const FftPlan&, int);
+template size_t fft_lds_bytes<float>(const FftPlan&, int);
 
 // ------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -373,8 +441,9 @@ __device__ __forceinline__ void forward_body(const Consts& c, const T* __restric
                                              double* __restrict__ dcsum, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* a = reinterpret_cast<C2<T>*>(smem);
-  C2<T>* b = a + pl.n;
+  C2<T>* b = a + pl.n;  // second transform buffer, or only the scratch when in place
   double* red = reinterpret_cast<double*>(b);  // idle until the transform
+  const bool ip = fft_in_place(pl, blockDim.x);
   const int j0 = 2 * bx, j1 = j0 + 1;
   const bool has1 = j1 < c.ny;
   const int j1c = has1 ? j1 : j0;  // a missing second row re-reads the first; dropped below
@@ -405,7 +474,7 @@ __device__ __forceinline__ void forward_body(const Consts& c, const T* __restric
     if (has1) dcsum[j1] = s1;
   }
   __syncthreads();
-  C2<T>* z = fft_lds<T, false>(a, b, pl, tw);
+  C2<T>* z = ip ? fft_lds_ip<T, false>(a, pl, tw) : fft_lds<T, false>(a, b, pl, tw);
   const T sc = T(-0.5 / c.eps);
   const int N = pl.n;
   for (int m = threadIdx.x; m < c.M; m += blockDim.x) {
@@ -422,7 +491,7 @@ __device__ __forceinline__ void forward_body(const Consts& c, const T* __restric
 }
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(1024) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
+__global__ void __launch_bounds__(512) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
                                                  const double* __restrict__ drc_field, FftPlan pl,
                                                  const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
                                                  double* __restrict__ dcsum) {
@@ -437,81 +506,123 @@ __global__ void __launch_bounds__(1024) k_forward(Consts c, const T* __restrict_
 //   D(-1) = (phi_upper - phi_lower)/ny - (S(ny-1) + 2 sum_{k<ny-1} S(k)) / (2 ny)
 //   phi_mean(j) = phi_lower + D(-1)/2 + sum_{k<j} D(k),  E_y mean = -(D(j) + D(j-1))/2
 // One block; FP64 throughout.
+// Exclusive prefix sum of v over the threads of the block in thread order
+// (blockDim.x a multiple of 64): a shuffle scan inside each wave, then the
+// wave totals in order.  `red` holds 16 doubles of LDS; `total` receives the
+// sum over the block.
+__device__ double block_exclusive_scan(double v, double* red, double& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) red[wave] = x;
+  __syncthreads();
+  double before = 0.0, all = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    const double t = red[w];
+    if (w < wave) before += t;
+    all += t;
+  }
+  total = all;
+  return before + (x - v);
+}
+
+// The column is swept in tiles of kMeanRows * blockDim.x rows; in a tile each
+// thread holds kMeanRows consecutive rows in registers (their loads all in
+// flight at once) and the running sums come from block scans of the thread
+// partials plus the carry of the earlier tiles.  A first sweep finds S(ny-1)
+// and the sum of S, hence D(-1); the second one writes the rows.  Both
+// sweeps form S(j) by the same operations, so they agree exactly.
+constexpr int kMeanRows = 8;
+
 __device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restrict__ rowsd,
                                                double* __restrict__ dmean) {
-  __shared__ double part[1024];
   __shared__ double red[32];
   const int ny = c.ny;
-  const int nt = blockDim.x;
-  const int chunk = (ny + nt - 1) / nt;
-  const int lo = threadIdx.x * chunk;
-  const int hi = min(lo + chunk, ny);
+  const int TB = kMeanRows * blockDim.x;
   const double* r = rowsd + ROWD_R * ny;
   const double* dcs = rowsd + ROWD_DCSUM * ny;
-  // local inclusive sums of sbar, stored in dmean[1 + j]
-  double acc = 0.0;
-  for (int j = lo; j < hi; ++j) {
-    const double sb = -(r[j] + dcs[j] / (double)c.nx) / c.eps;
-    acc += sb;
-    dmean[1 + j] = acc;
-  }
-  // exclusive scan of the chunk totals (Hillis-Steele over the block)
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 1; o < nt; o <<= 1) {
-    const double v = threadIdx.x >= o ? part[threadIdx.x - o] : 0.0;
+  const double inx = (double)c.nx;
+  // sbar(j) = -(r(j) + dcsum(j) / nx) / eps; S(j) = sum_{k <= j} sbar(k)
+  double carry = 0.0, tsum = 0.0;  // S before the tile; this thread's part of sum_{k < ny-1} S(k)
+  for (int t0 = 0; t0 < ny; t0 += TB) {
+    const int lo = t0 + (int)threadIdx.x * kMeanRows;
+    double sb[kMeanRows];
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMeanRows; ++q) {
+      const int j = min(lo + q, ny - 1);
+      const double v = -(r[j] + dcs[j] / inx) / c.eps;
+      sb[q] = lo + q < ny ? v : 0.0;
+      part += sb[q];
+    }
+    double tile;
+    double S = carry + block_exclusive_scan(part, red, tile);
+#pragma unroll
+    for (int q = 0; q < kMeanRows; ++q) {
+      S += sb[q];
+      if (lo + q < ny - 1) tsum += S;
+    }
+    carry += tile;
     __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
   }
-  const double off = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
-  double tsum = 0.0;  // sum of S(k) for k < ny - 1 over this chunk
-  for (int j = lo; j < hi; ++j) {
-    const double S = dmean[1 + j] + off;
-    dmean[1 + j] = S;
-    if (j < ny - 1) tsum += S;
-  }
-  const double Ttot = block_sum(tsum, red);
-  __syncthreads();
-  const double Slast = dmean[ny];
+  const double Slast = carry;
+  const double Ttot = block_sum(tsum, red + 16);
   const double dlow = (0.0 - 1.0) / (double)ny - (Slast + 2.0 * Ttot) / (2.0 * ny);
-  __syncthreads();
-  // D(j) = D(-1) + S(j); potential = exclusive running sum of D
-  double pacc = 0.0;
-  for (int j = lo; j < hi; ++j) {
-    const double D = dlow + dmean[1 + j];
-    dmean[1 + j] = D;
-    pacc += D;
-  }
-  __syncthreads();
-  part[threadIdx.x] = pacc;
-  __syncthreads();
-  for (int o = 1; o < nt; o <<= 1) {
-    const double v = threadIdx.x >= o ? part[threadIdx.x - o] : 0.0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  double run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
   const double phi0 = 1.0 + 0.5 * dlow;
   double* eym = rowsd + ROWD_EYM * ny;
   double* phim = rowsd + ROWD_PHIM * ny;
   double* dfy = rowsd + ROWD_DFY * ny;
   if (threadIdx.x == 0) dmean[0] = dlow;
-  for (int j = lo; j < hi; ++j) {
-    const double Dj = dmean[1 + j];
-    const double Djm = j > 0 ? dmean[j] : dlow;
-    phim[j] = phi0 + run;
-    const double e = -(Dj + Djm) / 2.0;
-    eym[j] = e;
-    dfy[j] = r[j] * e - c.s_ref / 3.0;
-    run += Dj;
+  // D(j) = D(-1) + S(j); the potential is the exclusive running sum of D
+  carry = 0.0;
+  double pcarry = 0.0;  // sum of D before the tile
+  for (int t0 = 0; t0 < ny; t0 += TB) {
+    const int lo = t0 + (int)threadIdx.x * kMeanRows;
+    double sb[kMeanRows], rr[kMeanRows];
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMeanRows; ++q) {
+      const int j = min(lo + q, ny - 1);
+      rr[q] = r[j];
+      const double v = -(rr[q] + dcs[j] / inx) / c.eps;
+      sb[q] = lo + q < ny ? v : 0.0;
+      part += sb[q];
+    }
+    double tile;
+    const double off = carry + block_exclusive_scan(part, red, tile);
+    double S = off, D[kMeanRows], pd = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMeanRows; ++q) {
+      S += sb[q];
+      D[q] = dlow + S;
+      if (lo + q < ny) pd += D[q];
+    }
+    __syncthreads();
+    double ptile;
+    double run = pcarry + block_exclusive_scan(pd, red, ptile);
+    double Dprev = dlow + off;  // D(lo - 1); D(-1) = dlow
+#pragma unroll
+    for (int q = 0; q < kMeanRows; ++q) {
+      const int j = lo + q;
+      if (j < ny) {
+        dmean[1 + j] = D[q];
+        phim[j] = phi0 + run;
+        const double e = -(D[q] + Dprev) / 2.0;
+        eym[j] = e;
+        dfy[j] = rr[q] * e - c.s_ref / 3.0;
+        run += D[q];
+        Dprev = D[q];
+      }
+    }
+    carry += tile;
+    pcarry += ptile;
+    __syncthreads();
   }
-}
-
-__global__ void __launch_bounds__(1024) k_mean_mode(Consts c, double* __restrict__ rowsd,
-                                                     double* __restrict__ dmean) {
-  mean_mode_body(c, rowsd, dmean);
 }
 
 // ------------------------------------------------- per-wavenumber solves
@@ -576,10 +687,19 @@ __device__ __forceinline__ void tri_local_body(const Consts& c, const T* __restr
   ends[(2 * (size_t)k + 1) * MP + m] = last;
 }
 
+// Block 0 solves the x-mean mode (independent of the m >= 1 solves, so it
+// runs beside them); blocks 1.. are the chunk-local solves.
 template <typename T>
-__global__ void __launch_bounds__(64) k_tri_local(Consts c, const T* __restrict__ tt, C2<T>* __restrict__ spec,
-                                                  C2<T>* __restrict__ ends) {
-  tri_local_body<T>(c, tt, spec, ends, blockIdx.x, blockIdx.y);
+__global__ void __launch_bounds__(256) k_tri_local(Consts c, const T* __restrict__ tt, C2<T>* __restrict__ spec,
+                                                   C2<T>* __restrict__ ends, double* __restrict__ rowsd,
+                                                   double* __restrict__ dmean) {
+  if (blockIdx.x == 0) {
+    mean_mode_body(c, rowsd, dmean);
+    return;
+  }
+  const int b = blockIdx.x - 1;
+  const int nbx = (c.M - 1 + blockDim.x - 1) / blockDim.x;
+  tri_local_body<T>(c, tt, spec, ends, b % nbx, b / nbx);
 }
 
 // One thread per m: the interface system.  Interface k (between chunks k
@@ -808,26 +928,28 @@ __device__ __forceinline__ void inverse_gather(const Consts& c, const C2<T>* __r
   const T* w1 = tt + ((size_t)(type * 3 + 2) * kChunk + i1) * MP;
   const C2<T>* Lp = iface + (2 * (size_t)(HL ? k - 1 : 0)) * MP;
   const C2<T>* Rp = iface + (2 * (size_t)k + 1) * MP;
+  // the lower half m < M is loaded once; the upper half N - m holds the
+  // conjugates (the two rows are real)
   constexpr int U = 4;
-  for (int m0 = threadIdx.x; m0 < N; m0 += U * blockDim.x) {
+  const int M = c.M;
+  for (int m0 = threadIdx.x; m0 < M; m0 += U * blockDim.x) {
     C2<T> X[U], Y[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int m = min(m0 + u * (int)blockDim.x, N - 1);
-      const int mm = m < c.M ? m : N - m;
-      X[u] = y0[mm];
-      Y[u] = y1[mm];
+      const int m = min(m0 + u * (int)blockDim.x, M - 1);
+      X[u] = y0[m];
+      Y[u] = y1[m];
       if (HL) {
-        const C2<T> L = Lp[mm];
-        const T a0 = v0[mm], a1 = v1[mm];
+        const C2<T> L = Lp[m];
+        const T a0 = v0[m], a1 = v1[m];
         X[u].re += a0 * L.re;
         X[u].im += a0 * L.im;
         Y[u].re += a1 * L.re;
         Y[u].im += a1 * L.im;
       }
       if (HR) {
-        const C2<T> R = Rp[mm];
-        const T b0 = w0[mm], b1 = w1[mm];
+        const C2<T> R = Rp[m];
+        const T b0 = w0[m], b1 = w1[m];
         X[u].re += b0 * R.re;
         X[u].im += b0 * R.im;
         Y[u].re += b1 * R.re;
@@ -837,13 +959,10 @@ __device__ __forceinline__ void inverse_gather(const Consts& c, const C2<T>* __r
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int m = m0 + u * (int)blockDim.x;
-      if (m < N) {
-        C2<T> x = X[u], y = has1 ? Y[u] : C2<T>{T(0), T(0)};
-        if (m >= c.M) {  // upper half: conjugates of the lower one
-          x.im = -x.im;
-          y.im = -y.im;
-        }
+      if (m < M) {
+        const C2<T> x = X[u], y = has1 ? Y[u] : C2<T>{T(0), T(0)};
         a[m] = m == 0 ? C2<T>{T(0), T(0)} : C2<T>{x.re - y.im, x.im + y.re};
+        if (m >= 1 && N - m >= M) a[N - m] = C2<T>{x.re + y.im, y.re - x.im};
       }
     }
   }
@@ -875,7 +994,7 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
   else
     inverse_gather<T, false, false>(c, spec, tt, iface, j0, has1, N, a);
   __syncthreads();
-  C2<T>* z = fft_lds<T, true>(a, b, pl, tw);
+  C2<T>* z = fft_in_place(pl, blockDim.x) ? fft_lds_ip<T, true>(a, pl, tw) : fft_lds<T, true>(a, b, pl, tw);
   const T inv = T(1.0 / (double)N);
   for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
     phi[(size_t)j0 * c.P + x] = z[x].re * inv;
@@ -884,7 +1003,7 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
+__global__ void __launch_bounds__(512) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
                                                  const C2<T>* __restrict__ iface, FftPlan pl,
                                                  const C2<T>* __restrict__ tw, T* __restrict__ phi) {
   inverse_body<T>(c, spec, tt, iface, pl, tw, phi, blockIdx.x);
@@ -1210,7 +1329,7 @@ __device__ __forceinline__ bool slot_emits(const SlotDesc& d) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) kb_forward(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+__global__ void __launch_bounds__(512) kb_forward(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
@@ -1218,22 +1337,19 @@ __global__ void __launch_bounds__(1024) kb_forward(const SlotDesc* __restrict__ 
                      (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny, blockIdx.x - off[s]);
 }
 
-__global__ void __launch_bounds__(1024) kb_mean_mode(const SlotDesc* __restrict__ D, const int* __restrict__ off,
-                                                     int ns) {
-  const int s = find_slot(off, ns, blockIdx.x);
-  const SlotDesc& d = D[s];
-  if (!d.active) return;
-  mean_mode_body(d.c, d.b.rowsd, d.b.dmean);
-}
-
 template <typename T>
-__global__ void __launch_bounds__(64) kb_tri_local(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+__global__ void __launch_bounds__(256) kb_tri_local(const SlotDesc* __restrict__ D, const int* __restrict__ off,
+                                                    int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
   const int lb = blockIdx.x - off[s];
-  const int nbx = (d.c.M - 1 + 63) / 64;
-  tri_local_body<T>(d.c, (const T*)d.b.tt, (C2<T>*)d.b.spec, (C2<T>*)d.b.ends, lb % nbx, lb / nbx);
+  if (lb == 0) {
+    mean_mode_body(d.c, d.b.rowsd, d.b.dmean);
+    return;
+  }
+  const int nbx = (d.c.M - 1 + blockDim.x - 1) / blockDim.x;
+  tri_local_body<T>(d.c, (const T*)d.b.tt, (C2<T>*)d.b.spec, (C2<T>*)d.b.ends, (lb - 1) % nbx, (lb - 1) / nbx);
 }
 
 // 256 threads per block: four wavenumbers per block on the scan path, 256 on
@@ -1255,7 +1371,7 @@ __global__ void __launch_bounds__(256) kb_tri_reduced(const SlotDesc* __restrict
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) kb_inverse(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
+__global__ void __launch_bounds__(512) kb_inverse(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
@@ -1332,8 +1448,7 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu) {
   switch (k) {
     case BK_FORWARD:
     case BK_INVERSE: return (c.ny + 1) / 2;
-    case BK_MEAN: return 1;
-    case BK_TRI_LOCAL: return nm > 0 ? ((nm + 63) / 64) * c.NC : 0;
+    case BK_TRI_LOCAL: return 1 + (nm > 0 ? ((nm + 255) / 256) * c.NC : 0);
     case BK_TRI_REDUCED:
       if (nm <= 0 || c.NC < 2) return 0;
       return c.NC - 1 <= kScanMax ? (nm + 3) / 4 : (nm + 255) / 256;
@@ -1350,10 +1465,8 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
   SlotDesc* D = const_cast<SlotDesc*>(d_desc);
   if (totals[BK_FORWARD])
     hipLaunchKernelGGL(kb_forward<T>, dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s, d_desc, d_off + BK_FORWARD * row, ns);
-  if (totals[BK_MEAN])
-    hipLaunchKernelGGL(kb_mean_mode, dim3(totals[BK_MEAN]), dim3(1024), 0, s, d_desc, d_off + BK_MEAN * row, ns);
   if (totals[BK_TRI_LOCAL])
-    hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(64), 0, s, d_desc,
+    hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(256), 0, s, d_desc,
                        d_off + BK_TRI_LOCAL * row, ns);
   if (totals[BK_TRI_REDUCED])
     hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(256), 0, s, d_desc,
@@ -1400,7 +1513,7 @@ template <typename T>
 hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src, const Tuning& tu,
                           hipStream_t s) {
   dim3 blk(tu.fft_threads), grd((c.ny + 1) / 2);
-  const size_t lds = fft_lds_bytes<T>(pl.n);
+  const size_t lds = fft_lds_bytes<T>(pl, tu.fft_threads);
   const T* G = (const T*)b.g[src];
   const T* rows = (const T*)b.rows;
   const double* fld = b.mom + 3 * (size_t)c.ny * c.nx;
@@ -1417,19 +1530,13 @@ hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int
 }
 
 template <typename T>
-hipError_t launch_mean_mode(const Consts& c, const Bufs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_mean_mode, dim3(1), dim3(1024), 0, s, c, b.rowsd, b.dmean);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
   const int nm = c.M - 1;
-  if (nm <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tri_local<T>, dim3((nm + 63) / 64, c.NC), dim3(64), 0, s, c, (const T*)b.tt,
-                     (C2<T>*)b.spec, (C2<T>*)b.ends);
+  const int nloc = nm > 0 ? ((nm + 255) / 256) * c.NC : 0;
+  hipLaunchKernelGGL(k_tri_local<T>, dim3(1 + nloc), dim3(256), 0, s, c, (const T*)b.tt, (C2<T>*)b.spec,
+                     (C2<T>*)b.ends, b.rowsd, b.dmean);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || c.NC < 2) return e;
+  if (e != hipSuccess || nm <= 0 || c.NC < 2) return e;
   if (c.NC - 1 <= kScanMax)
     hipLaunchKernelGGL(k_tri_scan<T>, dim3((nm + 3) / 4), dim3(256), 0, s, c, (const T*)b.rf,
                        (const C2<T>*)b.ends, (C2<T>*)b.iface);
@@ -1442,7 +1549,7 @@ hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
 template <typename T>
 hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, const Tuning& tu, hipStream_t s) {
   dim3 blk(tu.fft_threads), grd((c.ny + 1) / 2);
-  const size_t lds = fft_lds_bytes<T>(pl.n);
+  const size_t lds = fft_lds_bytes<T>(pl, tu.fft_threads);
   hipLaunchKernelGGL(k_inverse<T>, grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
                      (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
   return hipGetLastError();
@@ -1497,7 +1604,6 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
   template hipError_t launch_init_populations<T>(const Consts&, const Bufs&, int, hipStream_t);             \
   template hipError_t launch_forward<T>(const Consts&, const Bufs&, const FftPlan&, int, int, const Tuning&,   \
                                        hipStream_t);                                                        \
-  template hipError_t launch_mean_mode<T>(const Consts&, const Bufs&, hipStream_t);                         \
   template hipError_t launch_tridiag<T>(const Consts&, const Bufs&, hipStream_t);                           \
   template hipError_t launch_inverse<T>(const Consts&, const Bufs&, const FftPlan&, const Tuning&, hipStream_t); \
   template hipError_t launch_fields<T>(const Consts&, const Bufs&, double*, double*, double*, double*,       \

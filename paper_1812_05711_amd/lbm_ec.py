@@ -209,7 +209,7 @@ class Simulation:
     def set_tuning(self, fft_threads=256, collide_bx=64, collide_by=4):
         _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
 
-    KERNEL_CLASSES = ("forward", "mean_mode", "tridiag", "inverse", "collide")
+    KERNEL_CLASSES = ("forward", "tridiag", "inverse", "collide")
 
     def profile_begin(self):
         _check(lib().lbm_ec_profile_begin(self._h))
