@@ -153,13 +153,35 @@ int lbm_ec_fields(lbm_ec_t* h, double* rho, double* ux, double* uy,
 int lbm_ec_poisson(lbm_ec_t* h, const double* d_rho_c, double* d_phi);
 
 /* Global diagnostics of the current state, computed in FP64 on the device
- * and copied to host memory out[8] (waits for the stream):
+ * and copied to host memory out[10] (waits for the stream):
  *   out[0] steps done, out[1] sum of (rho - 1) over nodes, out[2] sum of
  *   rho_c (lattice units), out[3] rms of u_y (lattice units), out[4] max of
  *   |u| (lattice units), out[5] min rho_c, out[6] number of non-finite or
- *   non-positive-density nodes, out[7] max |E_x| (lattice units).
+ *   non-positive-density nodes, out[7] max |E_x| (lattice units),
+ *   out[8] charge the next streaming brings in through the injector and
+ *   out[9] net charge it brings in through the collector (negative: the
+ *   collector current), both summed over x in lattice units, from the
+ *   post-collision populations and the electrode rules of Table I (their
+ *   sum is the change of the total charge over that streaming).
  * Returns EUNSTABLE (after filling out) if out[6] > 0. */
 int lbm_ec_stats(lbm_ec_t* h, double* out);
+
+/* Checkpoint and restart (continuing a run, or branching several runs off
+ * one state).  A checkpoint holds the post-collision populations and every
+ * array lbm_ec_fields reads, in a device buffer of lbm_ec_checkpoint_bytes(h)
+ * bytes owned by the caller (any device memory, e.g. a torch uint8 tensor).
+ *   lbm_ec_save copies the instance's state into d_dst (ENOMEM if bytes is
+ *   smaller than needed); it waits for the stream.
+ *   lbm_ec_load replaces the instance's state with the checkpoint in d_src,
+ *   including its step count; EINVAL unless the checkpoint was taken with the
+ *   same grid, precision, charge-rate reading and physical parameters (T, C,
+ *   M, Fe, tau_plus, Lambda, Lambda_g, body force).  Stepping a loaded
+ *   instance gives bit for bit the results the saved one would have given.
+ *   It waits for the stream to read the header, then copies asynchronously.
+ * Checkpoints are not portable between library versions. */
+size_t lbm_ec_checkpoint_bytes(const lbm_ec_t* h);
+int lbm_ec_save(lbm_ec_t* h, void* d_dst, size_t bytes);
+int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes);
 
 /* Kernel timing for measurement.  lbm_ec_profile_begin starts recording a
  * HIP event pair around every kernel the handle enqueues on its stream;

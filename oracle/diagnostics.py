@@ -17,20 +17,28 @@ def total_charge(g):
     return float(g.sum())
 
 
-def charge_boundary_change(g_post, rho0):
-    """Net charge that streaming adds in one step, from the post-collision g*.
+def charge_boundary_fluxes(g_post, rho0):
+    """Charge that streaming the post-collision g* moves across each
+    electrode in one step: (in through the lower one, net in through the
+    upper one).
 
-    Lower electrode: each outgoing g*_i (c_iy = -1) is replaced by the
-    anti-bounce-back value -g*_i + 2 w_i rho0 in the opposite direction.
-    Upper electrode: outgoing directions (c_iy = +1) leave the channel and
-    the incoming ones (c_iy = -1) copy the last row.  Collision conserves
-    sum_i g_i, so Q^{n+1} - Q^n equals this.
+    Lower electrode (injector): each outgoing g*_i (c_iy = -1) is replaced
+    by the anti-bounce-back value -g*_i + 2 w_i rho0 in the opposite
+    direction.  Upper electrode (collector): outgoing directions (c_iy = +1)
+    leave the channel and the incoming ones (c_iy = -1) copy the last row.
     """
     down = CI[:, 1] == -1
     up = CI[:, 1] == 1
     lower = np.sum(2.0 * WI[down][:, None] * rho0 - 2.0 * g_post[down, 0, :])
     upper = np.sum(g_post[down, -1, :]) - np.sum(g_post[up, -1, :])
-    return float(lower + upper)
+    return float(lower), float(upper)
+
+
+def charge_boundary_change(g_post, rho0):
+    """Net charge that streaming adds in one step.  Collision conserves
+    sum_i g_i, so Q^{n+1} - Q^n equals this."""
+    lower, upper = charge_boundary_fluxes(g_post, rho0)
+    return lower + upper
 
 
 def rel_max_error(x, ref):

@@ -999,12 +999,13 @@ int lbm_ec_poisson(lbm_ec_t* h, const double* d_rho_c, double* d_phi) {
 
 int lbm_ec_stats(lbm_ec_t* h, double* out) {
   if (!h || !out) return fail(LBM_EC_EINVAL, "NULL argument");
-  EC_HIP(h->fp32 ? ec::launch_stats<float>(h->c, h->b, h->s) : ec::launch_stats<double>(h->c, h->b, h->s));
+  EC_HIP(h->fp32 ? ec::launch_stats<float>(h->c, h->b, h->cur, h->s)
+                 : ec::launch_stats<double>(h->c, h->b, h->cur, h->s));
   double tmp[16];
   EC_HIP(hipMemcpyAsync(tmp, h->b.stats, sizeof(tmp), hipMemcpyDeviceToHost, h->s));
   EC_HIP(hipStreamSynchronize(h->s));
   tmp[0] = (double)h->steps;
-  for (int i = 0; i < 8; ++i) out[i] = tmp[i];
+  for (int i = 0; i < 10; ++i) out[i] = tmp[i];
   if (tmp[6] > 0) return fail(LBM_EC_EUNSTABLE, "non-finite values or non-positive density in the state");
   return LBM_EC_OK;
 }
@@ -1037,6 +1038,115 @@ int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n) {
   }
   P.used = 0;
   P.cls.clear();
+  return LBM_EC_OK;
+}
+
+// ------------------------------------------------------------- checkpoints
+// A checkpoint is [header, padded to 256 B][f][g][phi][rows FP64][D][moments],
+// each region 256-byte aligned: the post-collision populations and
+// everything lbm_ec_fields reads, so a loaded instance continues bit for bit.
+namespace {
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'E', 'C', 'C', 'K', '1'};
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int32_t nx, ny, precision, charge_rates;
+  double T, C, M, Fe, tau_plus, Lambda, Lambda_g, body_force_x;
+  int64_t steps;
+  uint64_t total;
+};
+struct CkptLayout {
+  size_t pop, phi, rowsd, dmean, mom;  // region sizes
+  size_t off_f, off_g, off_phi, off_rowsd, off_dmean, off_mom, total;
+};
+CkptLayout ckpt_layout(const lbm_ec* h) {
+  CkptLayout K{};
+  const size_t ny = (size_t)h->p.ny, nx = (size_t)h->p.nx;
+  K.pop = 9 * ny * h->L.P * h->L.tsize;
+  K.phi = ny * h->L.P * h->L.tsize;
+  K.rowsd = (size_t)ec::ROWD_COUNT * ny * 8;
+  K.dmean = (ny + 1) * 8;
+  K.mom = 4 * ny * nx * 8;
+  size_t o = align_up(sizeof(CkptHeader));
+  K.off_f = o;
+  o = align_up(o + K.pop);
+  K.off_g = o;
+  o = align_up(o + K.pop);
+  K.off_phi = o;
+  o = align_up(o + K.phi);
+  K.off_rowsd = o;
+  o = align_up(o + K.rowsd);
+  K.off_dmean = o;
+  o = align_up(o + K.dmean);
+  K.off_mom = o;
+  K.total = align_up(o + K.mom);
+  return K;
+}
+void ckpt_fill(const lbm_ec* h, CkptHeader* H, uint64_t total) {
+  std::memset(H, 0, sizeof(*H));
+  std::memcpy(H->magic, kCkptMagic, 8);
+  H->version = 1;
+  H->header_bytes = (uint32_t)sizeof(CkptHeader);
+  const lbm_ec_params& p = h->p;
+  H->nx = p.nx;
+  H->ny = p.ny;
+  H->precision = p.precision;
+  H->charge_rates = p.charge_rates;
+  H->T = p.T;
+  H->C = p.C;
+  H->M = p.M;
+  H->Fe = p.Fe;
+  H->tau_plus = p.tau_plus;
+  H->Lambda = p.Lambda;
+  H->Lambda_g = p.Lambda_g;
+  H->body_force_x = p.body_force_x;
+  H->steps = h->steps;
+  H->total = total;
+}
+}  // namespace
+
+size_t lbm_ec_checkpoint_bytes(const lbm_ec_t* h) { return h ? ckpt_layout(h).total : 0; }
+
+int lbm_ec_save(lbm_ec_t* h, void* d_dst, size_t bytes) {
+  if (!h || !d_dst) return fail(LBM_EC_EINVAL, "NULL argument");
+  const CkptLayout K = ckpt_layout(h);
+  if (bytes < K.total) return fail(LBM_EC_ENOMEM, "checkpoint buffer too small: need " + std::to_string(K.total));
+  CkptHeader H;
+  ckpt_fill(h, &H, K.total);
+  unsigned char* d = (unsigned char*)d_dst;
+  EC_HIP(hipMemcpyAsync(d, &H, sizeof(H), hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_f, h->b.f[h->cur], K.pop, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_g, h->b.g[h->cur], K.pop, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_phi, h->b.phi, K.phi, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_rowsd, h->b.rowsd, K.rowsd, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_dmean, h->b.dmean, K.dmean, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_mom, h->b.mom, K.mom, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipStreamSynchronize(h->s));  // the header is read from host memory
+  return LBM_EC_OK;
+}
+
+int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes) {
+  if (!h || !d_src) return fail(LBM_EC_EINVAL, "NULL argument");
+  const CkptLayout K = ckpt_layout(h);
+  if (bytes < K.total) return fail(LBM_EC_EINVAL, "checkpoint buffer smaller than this instance's checkpoint");
+  CkptHeader H, mine;
+  const unsigned char* d = (const unsigned char*)d_src;
+  EC_HIP(hipMemcpyAsync(&H, d, sizeof(H), hipMemcpyDeviceToHost, h->s));
+  EC_HIP(hipStreamSynchronize(h->s));
+  ckpt_fill(h, &mine, K.total);
+  if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 1 || H.header_bytes != sizeof(CkptHeader))
+    return fail(LBM_EC_EINVAL, "not a checkpoint of this library version");
+  mine.steps = H.steps;
+  if (std::memcmp(&H, &mine, sizeof(H)) != 0)
+    return fail(LBM_EC_EINVAL, "checkpoint taken with other grid, precision or physical parameters");
+  h->cur = 0;
+  EC_HIP(hipMemcpyAsync(h->b.f[0], d + K.off_f, K.pop, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.g[0], d + K.off_g, K.pop, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.phi, d + K.off_phi, K.phi, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.rowsd, d + K.off_rowsd, K.rowsd, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.dmean, d + K.off_dmean, K.dmean, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.mom, d + K.off_mom, K.mom, hipMemcpyDeviceToDevice, h->s));
+  h->steps = H.steps;
   return LBM_EC_OK;
 }
 

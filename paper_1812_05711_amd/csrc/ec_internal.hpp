@@ -182,8 +182,9 @@ hipError_t launch_fields(const Consts& c, const Bufs& b, double* rho, double* ux
                          double* rho_c, double* phi, hipStream_t s);
 template <typename T>
 hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_nd, hipStream_t s);
+// cur: the buffer holding the post-collision populations (boundary charge)
 template <typename T>
-hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s);
+hipError_t launch_stats(const Consts& c, const Bufs& b, int cur, hipStream_t s);
 
 // LDS bytes of the x-transform kernels for plan pl on blocks of `threads`.
 template <typename T>

@@ -1252,12 +1252,31 @@ __global__ void __launch_bounds__(256) k_charge_in(Consts c, const double* __res
   mom[3 * n + k] = rc_nd[k] * c.eps / (c.H * c.H) - rowsd[ROWD_R * c.ny + j];
 }
 
-// Global FP64 diagnostics of the emitted moments (one block, fixed order).
+// Global FP64 diagnostics of the emitted moments (one block, fixed order),
+// and the charge that the next streaming of the post-collision populations
+// G moves across the electrodes (Table I): in through the injector (the
+// anti-bounce-back replaces each outgoing g*_i by 2 w_i rho0 - g*_i) and net
+// in through the collector (the incoming populations copy the last row, the
+// outgoing ones leave).  On deviations the reference rows cancel except in
+// the injector constants g_abb = 2 w_i (rho0 - r(0)).
 template <typename T>
 __global__ void __launch_bounds__(1024) k_stats(Consts c, const double* __restrict__ mom, const T* __restrict__ phi,
-                                                const double* __restrict__ rowsd, double* __restrict__ out) {
+                                                const double* __restrict__ rowsd, const T* __restrict__ G,
+                                                double* __restrict__ out) {
   __shared__ double red[32];
   const size_t n = (size_t)c.ny * c.nx;
+  const size_t plane = (size_t)c.ny * c.P, top = (size_t)(c.ny - 1) * c.P;
+  double q_in = 0, q_out = 0;
+  for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
+    q_in += (c.g_abb_axis - 2.0 * (double)G[4 * plane + x]) + (c.g_abb_diag - 2.0 * (double)G[7 * plane + x]) +
+            (c.g_abb_diag - 2.0 * (double)G[8 * plane + x]);
+    q_out += ((double)G[4 * plane + top + x] + (double)G[7 * plane + top + x] + (double)G[8 * plane + top + x]) -
+             ((double)G[2 * plane + top + x] + (double)G[5 * plane + top + x] + (double)G[6 * plane + top + x]);
+  }
+  q_in = block_sum(q_in, red);
+  __syncthreads();
+  q_out = block_sum(q_out, red);
+  __syncthreads();
   double s_drho = 0, s_rc = 0, s_uy2 = 0, mx_u = 0, mn_rc = 1e300, bad = 0, mx_ex = 0;
   for (size_t k = threadIdx.x; k < n; k += blockDim.x) {
     const int j = (int)(k / c.nx), x = (int)(k % c.nx);
@@ -1304,6 +1323,8 @@ __global__ void __launch_bounds__(1024) k_stats(Consts c, const double* __restri
     out[5] = mn[0];
     out[6] = bad;
     out[7] = me[0];
+    out[8] = q_in;
+    out[9] = q_out;
   }
 }
 
@@ -1594,8 +1615,9 @@ hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_
 }
 
 template <typename T>
-hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats<T>, dim3(1), dim3(1024), 0, s, c, b.mom, (const T*)b.phi, b.rowsd, b.stats);
+hipError_t launch_stats(const Consts& c, const Bufs& b, int cur, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats<T>, dim3(1), dim3(1024), 0, s, c, b.mom, (const T*)b.phi, b.rowsd, (const T*)b.g[cur],
+                     b.stats);
   return hipGetLastError();
 }
 
@@ -1609,7 +1631,7 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, hipStream_t s) {
   template hipError_t launch_fields<T>(const Consts&, const Bufs&, double*, double*, double*, double*,       \
                                        double*, hipStream_t);                                               \
   template hipError_t launch_charge_in<T>(const Consts&, const Bufs&, const double*, hipStream_t);          \
-  template hipError_t launch_stats<T>(const Consts&, const Bufs&, hipStream_t);
+  template hipError_t launch_stats<T>(const Consts&, const Bufs&, int, hipStream_t);
 
 EC_INSTANTIATE(double)
 EC_INSTANTIATE(float)

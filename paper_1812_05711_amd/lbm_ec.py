@@ -87,6 +87,12 @@ def lib():
     L.lbm_ec_profile_begin.restype = ctypes.c_int
     L.lbm_ec_profile_end.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
     L.lbm_ec_profile_end.restype = ctypes.c_int
+    L.lbm_ec_checkpoint_bytes.argtypes = [vp]
+    L.lbm_ec_checkpoint_bytes.restype = ctypes.c_size_t
+    L.lbm_ec_save.argtypes = [vp, vp, ctypes.c_size_t]
+    L.lbm_ec_save.restype = ctypes.c_int
+    L.lbm_ec_load.argtypes = [vp, vp, ctypes.c_size_t]
+    L.lbm_ec_load.restype = ctypes.c_int
     i32 = ctypes.c_int32
     L.lbm_ec_batch_workspace_bytes.argtypes = [P, i32, i32, i32]
     L.lbm_ec_batch_workspace_bytes.restype = ctypes.c_size_t
@@ -199,15 +205,29 @@ class Simulation:
         return phi
 
     def stats(self):
-        buf = (ctypes.c_double * 8)()
+        buf = (ctypes.c_double * 10)()
         code = lib().lbm_ec_stats(self._h, buf)
         if code not in (OK, EUNSTABLE):
             _check(code)
-        names = ["steps", "mass_dev", "charge", "rms_uy", "max_u", "min_rho_c", "bad", "max_ex"]
+        names = ["steps", "mass_dev", "charge", "rms_uy", "max_u", "min_rho_c", "bad", "max_ex", "q_injector",
+                 "q_collector"]
         return dict(zip(names, list(buf))), code == OK
 
     def set_tuning(self, fft_threads=256, collide_bx=64, collide_by=4):
         _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+
+    def save(self) -> torch.Tensor:
+        """Checkpoint of the current state in a new device uint8 tensor."""
+        n = lib().lbm_ec_checkpoint_bytes(self._h)
+        buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().lbm_ec_save(self._h, ctypes.c_void_p(buf.data_ptr()), n))
+        return buf
+
+    def load(self, buf: torch.Tensor):
+        """Replaces the state with a checkpoint taken by save() on an
+        instance with the same grid and parameters."""
+        assert buf.is_cuda and buf.dtype == torch.uint8 and buf.is_contiguous()
+        _check(lib().lbm_ec_load(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
 
     KERNEL_CLASSES = ("forward", "tridiag", "inverse", "collide")
 

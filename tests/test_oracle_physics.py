@@ -114,6 +114,17 @@ def test_hydrostatic_c01_matches_closed_form_and_table2():
     dp = np.diff(m["rho"][:, 0]) / 3.0
     assert np.max(np.abs(dp - 0.5 * (F[1:] + F[:-1]))) < 5e-3 * np.max(np.abs(F))
     assert np.max(np.abs(m["uy"])) < 1e-3 * o.lc.u0
+    # the charge the mesoscopic electrode rules move per step equals the
+    # macroscopic current rho_c (u_y + K E_y) - D_c d(rho_c)/dy in the bulk,
+    # and in the steady state what enters at the injector leaves at the collector
+    ft_post, gt_post = o.collide(m)
+    _, g_post = o.full(ft_post, gt_post)
+    q_in, q_out = diagnostics.charge_boundary_fluxes(g_post, o.lc.rho0)
+    j = 50
+    rcl = m["rho_c"][:, 0]
+    J = rcl[j] * (m["uy"][j, 0] + o.lc.K * m["ey"][j, 0]) - o.lc.Dc * (rcl[j + 1] - rcl[j - 1]) / 2.0
+    assert q_in > 0 and abs(q_in + q_out) < 2e-5 * q_in, (q_in, q_out)
+    assert abs(q_in - J) < 2e-4 * q_in, (q_in, J)
 
 
 def test_hydrostatic_c10_fit_reproduces_table2():
