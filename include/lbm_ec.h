@@ -195,9 +195,10 @@ int lbm_ec_profile_begin(lbm_ec_t* h);
 int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 
 /* Launch shapes, which never change results: threads per x-transform block
- * (64, 128, 256 or 512) and the collide block shape (collide_bx x collide_by
- * threads, product 64, 128 or 256).  Defaults 256 and 64 x 4.  Applies to the
- * following steps; EINVAL for other values.  The autotuner in
+ * (64, 128, 256 or 512) and threads per collide tile (collide_bx *
+ * collide_by, a multiple of 64 up to 1024; a tile is a band of whole rows
+ * whose height depends on ny only).  Defaults 256 and 256 x 1.  Applies to
+ * the following steps; EINVAL for other values.  The autotuner in
  * paper_1812_05711_amd/autotune.py picks them by timing. */
 int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by);
 

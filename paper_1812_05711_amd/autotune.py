@@ -1,5 +1,5 @@
 """Autotuner for the launch shapes of the time step (they never change
-results): threads per x-transform block and the collide block shape.
+results): threads per x-transform block and per collide tile.
 
 Candidates are timed with events on the batch's stream, on a throwaway batch
 of the same composition (so the real run is not advanced), and the best is
@@ -11,8 +11,8 @@ import json
 import os
 
 FFT_THREADS = (128, 256, 512)
-COLLIDE_SHAPES = ((64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (256, 1), (32, 4), (32, 8))
-DEFAULT = (256, 64, 4)
+COLLIDE_SHAPES = ((64, 1), (128, 1), (256, 1), (512, 1), (1024, 1))
+DEFAULT = (256, 256, 1)
 
 
 def cache_path():

@@ -81,7 +81,8 @@ ec::FftPlan make_plan(int n) {
 struct Layout {
   int P, M, MP, NC, KP;
   size_t tsize;
-  size_t off_f[2], off_g[2], off_phi, off_spec, off_tt, off_ends, off_gh, off_rf, off_iface, off_tw, off_rows,
+  size_t off_f[2], off_g[2], off_phi, off_rq, off_eu, off_ed, off_spec, off_tt, off_ends, off_gh, off_rf, off_iface,
+      off_tw, off_rows,
       off_rowsd, off_dmean, off_mom, off_stats, total;
 };
 
@@ -111,6 +112,10 @@ Layout make_layout(const lbm_ec_params& p) {
   L.off_g[0] = take(pop);
   L.off_g[1] = take(pop);
   L.off_phi = take(ny * L.P * L.tsize);
+  const size_t tiles = (ny + ec::tile_rows(p.ny) - 1) / ec::tile_rows(p.ny);
+  L.off_rq = take(ny * L.P * L.tsize);
+  L.off_eu = take(tiles * L.P * L.tsize);
+  L.off_ed = take(tiles * L.P * L.tsize);
   L.off_spec = take(ny * L.MP * 2 * L.tsize);
   L.off_tt = take(4 * 3 * (size_t)ec::kChunk * L.MP * L.tsize);
   L.off_ends = take(nc * 2 * L.MP * 2 * L.tsize);
@@ -209,6 +214,7 @@ int setup(lbm_ec* h, unsigned char* ws) {
   c.MP = L.MP;
   c.NC = L.NC;
   c.KP = L.KP;
+  c.TH = ec::tile_rows(ny);
   c.wp = 1.0 / p.tau_plus;
   c.wm = 1.0 / tau_m;
   c.wgp = 1.0 / tau_gp;
@@ -269,6 +275,12 @@ int setup(lbm_ec* h, unsigned char* ws) {
       rows[ec::ROW_DG_DN_AXIS * ny + j] = (T)(4.0 * q[j + 1] - 4.0 * q[j]);
       rows[ec::ROW_DG_DN_DIAG * ny + j] = (T)(q[j + 1] - q[j]);
     }
+    // the pull adds, to the charge populations of row j, ua + 2 ud from
+    // below (or the injector constants) and da + 2 dd from above (none at
+    // the collector)
+    const double below = j > 0 ? 6.0 * (q[j - 1] - q[j]) : c.g_abb_axis + 2.0 * c.g_abb_diag;
+    const double above = j < ny - 1 ? 6.0 * (q[j + 1] - q[j]) : 0.0;
+    rows[ec::ROW_KQ * ny + j] = (T)(below + above);
     rowsd[ec::ROWD_RHO_REF * ny + j] = rho_ref[j];
     rowsd[ec::ROWD_R * ny + j] = 36.0 * q[j];
     rowsd[ec::ROWD_RC_CLOSED * ny + j] = rc_closed[j];
@@ -450,6 +462,9 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
   h->b.g[0] = ws + L.off_g[0];
   h->b.g[1] = ws + L.off_g[1];
   h->b.phi = ws + L.off_phi;
+  h->b.rq = ws + L.off_rq;
+  h->b.eu = ws + L.off_eu;
+  h->b.ed = ws + L.off_ed;
   h->b.spec = ws + L.off_spec;
   h->b.tt = ws + L.off_tt;
   h->b.ends = ws + L.off_ends;
@@ -521,6 +536,7 @@ struct lbm_ec_batch {
   std::vector<int> order;  // slot index of each descriptor entry
   int totals[ec::BK_COUNT];
   size_t lds;
+  size_t collide_lds;
   bool dirty;
   hipGraphExec_t g_many, g_one;
   bool have_graphs;
@@ -582,7 +598,8 @@ int capture(lbm_ec_batch* B, int steps, hipGraphExec_t* out) {
   EC_HIP(hipStreamBeginCapture(B->s, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < steps && le == hipSuccess; ++k)
-    le = ec::launch_batch_step<T, C>(B->d_desc, B->d_off, B->totals, (int)B->order.size(), B->lds, B->tu, B->s);
+    le = ec::launch_batch_step<T, C>(B->d_desc, B->d_off, B->totals, (int)B->order.size(), B->lds, B->collide_lds,
+                                     B->tu, B->s);
   hipError_t ee = hipStreamEndCapture(B->s, &g);
   if (le != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture launch: ") + hipGetErrorString(le));
   if (ee != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture: ") + hipGetErrorString(ee));
@@ -622,6 +639,7 @@ int rebuild(lbm_ec_batch* B) {
   std::vector<ec::SlotDesc> D(ns);
   std::vector<int> off((size_t)ec::BK_COUNT * (ns + 1), 0);
   B->lds = 0;
+  B->collide_lds = 0;
   for (int k = 0; k < ec::BK_COUNT; ++k) B->totals[k] = 0;
   for (int q = 0; q < ns; ++q) {
     Slot& sl = B->slots[B->order[q]];
@@ -639,6 +657,9 @@ int rebuild(lbm_ec_batch* B) {
     const size_t lds = sl.inst.fp32 ? ec::fft_lds_bytes<float>(sl.inst.plan, B->tu.fft_threads)
                                     : ec::fft_lds_bytes<double>(sl.inst.plan, B->tu.fft_threads);
     B->lds = std::max(B->lds, lds);
+    const size_t clds = sl.inst.fp32 ? ec::collide_lds_bytes<float>(sl.inst.p.nx)
+                                     : ec::collide_lds_bytes<double>(sl.inst.p.nx);
+    B->collide_lds = std::max(B->collide_lds, clds);
     for (int k = 0; k < ec::BK_COUNT; ++k) {
       off[(size_t)k * (ns + 1) + q] = B->totals[k];
       B->totals[k] += ec::batch_blocks(d.c, k, B->tu);
@@ -853,9 +874,9 @@ void lbm_ec_batch_destroy(lbm_ec_batch_t* B) {
 static int check_tuning(int32_t fft_threads, int32_t bx, int32_t by) {
   if (fft_threads != 64 && fft_threads != 128 && fft_threads != 256 && fft_threads != 512)
     return fail(LBM_EC_EINVAL, "fft_threads must be 64, 128, 256 or 512");
-  const int t = bx * by;
-  if (bx < 1 || by < 1 || (t != 64 && t != 128 && t != 256))
-    return fail(LBM_EC_EINVAL, "collide block bx * by must be 64, 128 or 256");
+  const int64_t t = (int64_t)bx * by;
+  if (bx < 1 || by < 1 || t % 64 != 0 || t > 1024)
+    return fail(LBM_EC_EINVAL, "collide block bx * by must be a multiple of 64 up to 1024");
   return LBM_EC_OK;
 }
 
@@ -932,6 +953,9 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
   h->b.g[0] = ws + L.off_g[0];
   h->b.g[1] = ws + L.off_g[1];
   h->b.phi = ws + L.off_phi;
+  h->b.rq = ws + L.off_rq;
+  h->b.eu = ws + L.off_eu;
+  h->b.ed = ws + L.off_ed;
   h->b.spec = ws + L.off_spec;
   h->b.tt = ws + L.off_tt;
   h->b.ends = ws + L.off_ends;
@@ -1042,9 +1066,11 @@ int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n) {
 }
 
 // ------------------------------------------------------------- checkpoints
-// A checkpoint is [header, padded to 256 B][f][g][phi][rows FP64][D][moments],
-// each region 256-byte aligned: the post-collision populations and
-// everything lbm_ec_fields reads, so a loaded instance continues bit for bit.
+// A checkpoint is [header, padded to 256 B][f][g][charge sums][tile edges]
+// [phi][rows FP64][D][moments], each region 256-byte aligned: the
+// post-collision populations with the charge density the collide tiles
+// summed from them, and everything lbm_ec_fields reads, so a loaded
+// instance continues bit for bit.
 namespace {
 constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'E', 'C', 'C', 'K', '1'};
 struct CkptHeader {
@@ -1056,14 +1082,15 @@ struct CkptHeader {
   uint64_t total;
 };
 struct CkptLayout {
-  size_t pop, phi, rowsd, dmean, mom;  // region sizes
-  size_t off_f, off_g, off_phi, off_rowsd, off_dmean, off_mom, total;
+  size_t pop, phi, edges, rowsd, dmean, mom;  // region sizes
+  size_t off_f, off_g, off_rq, off_eu, off_ed, off_phi, off_rowsd, off_dmean, off_mom, total;
 };
 CkptLayout ckpt_layout(const lbm_ec* h) {
   CkptLayout K{};
   const size_t ny = (size_t)h->p.ny, nx = (size_t)h->p.nx;
   K.pop = 9 * ny * h->L.P * h->L.tsize;
   K.phi = ny * h->L.P * h->L.tsize;
+  K.edges = (size_t)ec::collide_tiles(h->c) * h->L.P * h->L.tsize;
   K.rowsd = (size_t)ec::ROWD_COUNT * ny * 8;
   K.dmean = (ny + 1) * 8;
   K.mom = 4 * ny * nx * 8;
@@ -1072,6 +1099,12 @@ CkptLayout ckpt_layout(const lbm_ec* h) {
   o = align_up(o + K.pop);
   K.off_g = o;
   o = align_up(o + K.pop);
+  K.off_rq = o;
+  o = align_up(o + K.phi);
+  K.off_eu = o;
+  o = align_up(o + K.edges);
+  K.off_ed = o;
+  o = align_up(o + K.edges);
   K.off_phi = o;
   o = align_up(o + K.phi);
   K.off_rowsd = o;
@@ -1085,7 +1118,7 @@ CkptLayout ckpt_layout(const lbm_ec* h) {
 void ckpt_fill(const lbm_ec* h, CkptHeader* H, uint64_t total) {
   std::memset(H, 0, sizeof(*H));
   std::memcpy(H->magic, kCkptMagic, 8);
-  H->version = 1;
+  H->version = 2;
   H->header_bytes = (uint32_t)sizeof(CkptHeader);
   const lbm_ec_params& p = h->p;
   H->nx = p.nx;
@@ -1117,6 +1150,9 @@ int lbm_ec_save(lbm_ec_t* h, void* d_dst, size_t bytes) {
   EC_HIP(hipMemcpyAsync(d, &H, sizeof(H), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemcpyAsync(d + K.off_f, h->b.f[h->cur], K.pop, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(d + K.off_g, h->b.g[h->cur], K.pop, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_rq, h->b.rq, K.phi, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_eu, h->b.eu, K.edges, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(d + K.off_ed, h->b.ed, K.edges, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(d + K.off_phi, h->b.phi, K.phi, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(d + K.off_rowsd, h->b.rowsd, K.rowsd, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(d + K.off_dmean, h->b.dmean, K.dmean, hipMemcpyDeviceToDevice, h->s));
@@ -1134,7 +1170,7 @@ int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes) {
   EC_HIP(hipMemcpyAsync(&H, d, sizeof(H), hipMemcpyDeviceToHost, h->s));
   EC_HIP(hipStreamSynchronize(h->s));
   ckpt_fill(h, &mine, K.total);
-  if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 1 || H.header_bytes != sizeof(CkptHeader))
+  if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 2 || H.header_bytes != sizeof(CkptHeader))
     return fail(LBM_EC_EINVAL, "not a checkpoint of this library version");
   mine.steps = H.steps;
   if (std::memcmp(&H, &mine, sizeof(H)) != 0)
@@ -1142,6 +1178,9 @@ int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes) {
   h->cur = 0;
   EC_HIP(hipMemcpyAsync(h->b.f[0], d + K.off_f, K.pop, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.g[0], d + K.off_g, K.pop, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.rq, d + K.off_rq, K.phi, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.eu, d + K.off_eu, K.edges, hipMemcpyDeviceToDevice, h->s));
+  EC_HIP(hipMemcpyAsync(h->b.ed, d + K.off_ed, K.edges, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.phi, d + K.off_phi, K.phi, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.rowsd, d + K.off_rowsd, K.rowsd, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.dmean, d + K.off_dmean, K.dmean, hipMemcpyDeviceToDevice, h->s));

@@ -30,6 +30,11 @@ __host__ __device__ inline bool fft_in_place(const FftPlan& pl, int threads) {
   return pl.n <= kFftPerThread * threads;
 }
 
+// Rows per collide tile, a function of the grid alone: the tile edges fix
+// the summation order of the next step's charge density, so the launch
+// shape must not move them.
+__host__ __device__ inline int tile_rows(int ny) { return ny >= 512 ? (ny / 256 < 16 ? ny / 256 : 16) : 1; }
+
 // Rows per chunk of the partitioned per-wavenumber solves.
 constexpr int kChunk = 32;
 // Chunk types: the whole column (one chunk), the first one (lower electrode
@@ -45,6 +50,7 @@ struct Consts {
   int MP;      // row pitch of spectral arrays, elements
   int NC;      // number of y chunks, ceil(ny / kChunk)
   int KP;      // row pitch of the interface factor table (NC - 1 rounded up to 8)
+  int TH;      // rows per collide tile (tile_rows(ny))
   double wp, wm, wgp, wgm;  // TRT rates: fluid +/-, charge +/-
   double K;                 // ion mobility
   double eps;               // permittivity
@@ -77,6 +83,8 @@ constexpr int kScanMax = 64 * kScanPerLane;
 // Factors of the interface system per (m, k), in this order (table rf).
 enum ReducedFactor { RF_INV = 0, RF_IB, RF_A, RF_P, RF_Q, RF_C, RF_G, RF_COUNT };
 
+__host__ __device__ inline int collide_tiles(const Consts& c) { return (c.ny + c.TH - 1) / c.TH; }
+
 // Per-row tables in the storage type (index k * ny + j).
 enum RowTable {
   ROW_RHO_REF = 0,   // hydrostatic reference density rho_ref(j)
@@ -85,6 +93,7 @@ enum RowTable {
   ROW_DG_UP_DIAG,
   ROW_DG_DN_AXIS,    // R_axis(j+1) - R_axis(j): g arriving from above
   ROW_DG_DN_DIAG,
+  ROW_KQ,            // sum of the constants the pull adds to the charge populations of row j
   ROW_COUNT
 };
 
@@ -110,6 +119,9 @@ struct Bufs {
   void* ends;    // [P][2][MP] complex: first / last row of each chunk's local solution
   void* gh;      // [P][6][MP]: block-elimination scratch of the interface system
   void* rf;      // [MP][7][KP]: data-independent factors of the interface system
+  void* rq;      // [ny][P] charge density deviation of the next step, summed by the collide tiles
+  void* eu;      // [tiles][P] contribution of each tile's last row to the row above it
+  void* ed;      // [tiles][P] contribution of each tile's first row to the row below it
   void* iface;   // [P][2][MP] complex: interface values a_k (last row of chunk k),
                  //                      b_k (first row of chunk k+1)
   void* tw;      // [nx] complex twiddles exp(-2 pi i k / nx)
@@ -136,10 +148,10 @@ struct SlotDesc {
 };
 
 // Launch shapes that do not change results: threads per x-transform block
-// and the collide block (bx x by threads, bx * by in {64, 128, 256}).
+// and per collide tile (cbx * cby threads, a multiple of 64 up to 1024).
 struct Tuning {
   int fft_threads = 256;
-  int cbx = 64, cby = 4;
+  int cbx = 256, cby = 1;
 };
 
 // Batched kernels; slot s owns the blocks [off[k][s], off[k][s+1]) of launch k.
@@ -153,7 +165,7 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu);
 // block count of launch k; lds the dynamic LDS of the transforms.
 template <typename T, typename C>
 hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
-                             const Tuning& tu, hipStream_t s);
+                             size_t collide_lds, const Tuning& tu, hipStream_t s);
 
 // Kernel launchers (ec_kernels.hip).  All enqueue on `s` and return the
 // launch status.
@@ -185,6 +197,10 @@ hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_
 // cur: the buffer holding the post-collision populations (boundary charge)
 template <typename T>
 hipError_t launch_stats(const Consts& c, const Bufs& b, int cur, hipStream_t s);
+
+// LDS bytes of a collide tile (ten rows of nx values of T).
+template <typename T>
+size_t collide_lds_bytes(int nx);
 
 // LDS bytes of the x-transform kernels for plan pl on blocks of `threads`.
 template <typename T>

@@ -277,6 +277,13 @@ size_t fft_lds_bytes(const FftPlan& pl, int threads) {
 template size_t fft_lds_bytes<double>(const FftPlan&, int);
 template size_t fft_lds_bytes<float>(const FftPlan&, int);
 
+template <typename T>
+size_t collide_lds_bytes(int nx) {
+  return 10 * (size_t)nx * sizeof(T);
+}
+template size_t collide_lds_bytes<double>(int);
+template size_t collide_lds_bytes<float>(int);
+
 // ------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -379,19 +386,33 @@ __device__ __forceinline__ void local_pop(const Consts& c, const T* __restrict__
   for (int i = 0; i < 9; ++i) a[i] = A[i * plane + idx];
 }
 
-// Charge density deviation rho_c - r at (x, j) at the start of the step:
-// MODE 0 pulls the post-collision populations (the streaming of Eq. 9),
-// MODE 1 sums the populations at the node, MODE 2 reads a given FP64 field.
+// Where the forward transform takes the charge density deviation rho_c - r
+// of the step from.
+template <typename T>
+struct ChargeSrc {
+  const T* rq;          // MODE 0: the collide tiles' sums (see collide_tile)
+  const T* eu;          //         and their edge rows
+  const T* ed;
+  const T* G;           // MODE 1: populations summed at the node
+  const double* field;  // MODE 2: a given FP64 field [ny][nx]
+};
+
+// rho_c - r at (x, j): MODE 0 completes the sums of the collide tiles with
+// the contributions that cross the tile edges, MODE 1 sums the populations
+// at the node (the initial state), MODE 2 reads the given field.
 template <typename T, int MODE>
-__device__ __forceinline__ T charge_at(const Consts& c, const T* __restrict__ G, const T* __restrict__ rows,
-                                       const double* __restrict__ drc_field, int x, int j) {
-  if (MODE == 2) return T(drc_field[(size_t)j * c.nx + x]);
-  T g[9];
-  if (MODE == 0)
-    pull_g<T>(c, G, rows, x, j, g);
-  else
-    local_pop<T>(c, G, x, j, g);
-  return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+__device__ __forceinline__ T charge_at(const Consts& c, const ChargeSrc<T>& q, int x, int j) {
+  if (MODE == 2) return T(q.field[(size_t)j * c.nx + x]);
+  if (MODE == 1) {
+    T g[9];
+    local_pop<T>(c, q.G, x, j, g);
+    return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+  }
+  T v = q.rq[(size_t)j * c.P + x];
+  const int H = c.TH, b = j / H, j0 = b * H, j1 = min(j0 + H, c.ny);
+  if (j == j0 && j > 0) v += q.eu[(size_t)(b - 1) * c.P + x];
+  if (j == j1 - 1 && j1 < c.ny) v += q.ed[(size_t)(b + 1) * c.P + x];
+  return v;
 }
 
 // FP64 sums of the real and the imaginary parts of a[0 .. n) in an order
@@ -435,8 +456,7 @@ __device__ __forceinline__ void row_sums_fixed_order(const C2<T>* __restrict__ a
 // s_m = -DFT(rho_c - r)_m / eps for m = 1 .. nx/2 (Eq. 4, 19) and the FP64
 // row sums of the charge deviation (the m = 0 mode).
 template <typename T, int MODE>
-__device__ __forceinline__ void forward_body(const Consts& c, const T* __restrict__ G, const T* __restrict__ rows,
-                                             const double* __restrict__ drc_field, const FftPlan& pl,
+__device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>& q, const FftPlan& pl,
                                              const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
                                              double* __restrict__ dcsum, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -455,8 +475,8 @@ __device__ __forceinline__ void forward_body(const Consts& c, const T* __restric
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int x = min(x0 + u * (int)blockDim.x, c.nx - 1);
-      v0[u] = charge_at<T, MODE>(c, G, rows, drc_field, x, j0);
-      v1[u] = charge_at<T, MODE>(c, G, rows, drc_field, x, j1c);
+      v0[u] = charge_at<T, MODE>(c, q, x, j0);
+      v1[u] = charge_at<T, MODE>(c, q, x, j1c);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -491,11 +511,9 @@ __device__ __forceinline__ void forward_body(const Consts& c, const T* __restric
 }
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(512) k_forward(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
-                                                 const double* __restrict__ drc_field, FftPlan pl,
-                                                 const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
-                                                 double* __restrict__ dcsum) {
-  forward_body<T, MODE>(c, G, rows, drc_field, pl, tw, spec, dcsum, blockIdx.x);
+__global__ void __launch_bounds__(512) k_forward(Consts c, ChargeSrc<T> q, FftPlan pl, const C2<T>* __restrict__ tw,
+                                                 C2<T>* __restrict__ spec, double* __restrict__ dcsum) {
+  forward_body<T, MODE>(c, q, pl, tw, spec, dcsum, blockIdx.x);
 }
 
 // --------------------------------------------------- x-mean mode (m = 0)
@@ -1017,15 +1035,14 @@ __global__ void __launch_bounds__(512) k_inverse(Consts c, const C2<T>* __restri
 // row in FP64), the equilibria (Eq. 10-11), the source (Eq. 12) and the TRT
 // collisions (Eq. 8-9, 13-15); writes the post-collision deviations.
 // mom == nullptr: no moments are emitted.
+// gout receives the post-collision charge populations as stored (rounded
+// to T), for the charge density of the next step.
 template <typename T, typename C, bool PULL>
-__device__ __forceinline__ void collide_body(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
+__device__ __forceinline__ void collide_node(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
                                              T* __restrict__ Fout, T* __restrict__ Gout,
                                              const T* __restrict__ phi, const T* __restrict__ rows,
-                                             const double* __restrict__ rowsd, double* __restrict__ mom, int bx,
-                                             int by) {
-  const int x = bx * blockDim.x + threadIdx.x;
-  const int j = by * blockDim.y + threadIdx.y;
-  if (x >= c.nx || j >= c.ny) return;
+                                             const double* __restrict__ rowsd, double* __restrict__ mom, int x, int j,
+                                             T gout[9]) {
   C f[9], g[9];
   {
     T ft[9], gt[9];
@@ -1131,21 +1148,97 @@ __device__ __forceinline__ void collide_body(const Consts& c, const T* __restric
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     Fout[i * plane + idx] = (T)fo[i];
-    Gout[i * plane + idx] = (T)go[i];
+    gout[i] = (T)go[i];
+    Gout[i * plane + idx] = gout[i];
+  }
+}
+
+// One block per tile of whole rows [j0, j1): it collides the rows in order
+// and forms, from the post-collision charge populations it has just
+// written, the charge density the next step's pull will see, rho_c^{n+1}
+// (x, j) = sum_i g*_i(x - c_i, j - c_iy) with the electrode rules of
+// Table I and the re-reference constants of the deviations (k_q(j), one per
+// row).  Row r contributes
+//   S(x) = g*_0(x) + g*_1(x-1) + g*_3(x+1)      to row r,
+//   U(x) = g*_2(x) + g*_5(x-1) + g*_6(x+1)      to row r+1,
+//   D(x) = g*_4(x) + g*_8(x-1) + g*_7(x+1)      to row r-1;
+// the injector row takes -(g*_4 + g*_7 + g*_8)(x) (anti-bounce-back, same
+// node) in place of U from below, the collector row takes its own D in place
+// of D from above.  The x neighbours come through LDS (whole rows, so x is
+// periodic inside the block); the y direction is marched.  Written: rq (the
+// density of rows j0 .. j1-1, without U from row j0-1 and without D from row
+// j1), eu[b] = U of row j1-1 and ed[b] = D of row j0 (the forward transform
+// adds them across the tile edges).  All sums in T, in a fixed order.
+//
+// LDS: ten arrays of nx values of T: the six x movers of the current row,
+// own g*_4, the incomplete P of the current and of the previous row, U.
+template <typename T, typename C, bool PULL, bool EMIT>
+__device__ __forceinline__ void collide_tile(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
+                                             T* __restrict__ Fout, T* __restrict__ Gout, const T* __restrict__ phi,
+                                             const T* __restrict__ rows, const double* __restrict__ rowsd,
+                                             double* __restrict__ mom, T* __restrict__ rq, T* __restrict__ eu,
+                                             T* __restrict__ ed, int b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = c.nx, ny = c.ny;
+  T* L = reinterpret_cast<T*>(smem);
+  T* m1 = L;            // g*_1, g*_5, g*_8 move to x+1
+  T* m5 = L + nx;
+  T* m8 = L + 2 * nx;
+  T* m3 = L + 3 * nx;   // g*_3, g*_6, g*_7 move to x-1
+  T* m6 = L + 4 * nx;
+  T* m7 = L + 5 * nx;
+  T* o4 = L + 6 * nx;   // own g*_4
+  T* Pa = L + 7 * nx;   // P of rows r and r-1 (swapped every row)
+  T* Pb = L + 8 * nx;
+  T* Ua = L + 9 * nx;   // U of the previous row, then of the current one
+  const int H = c.TH;
+  const int j0 = b * H, j1 = min(j0 + H, ny);
+  const T* kq = rows + ROW_KQ * ny;
+  for (int r = j0; r < j1; ++r) {
+    T* Pcur = ((r - j0) & 1) ? Pb : Pa;   // P(r) being built
+    T* Pprev = ((r - j0) & 1) ? Pa : Pb;  // P(r-1), complete
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+      T gt[9];
+      collide_node<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, x, r, gt);
+      m1[x] = gt[1];
+      m5[x] = gt[5];
+      m8[x] = gt[8];
+      m3[x] = gt[3];
+      m6[x] = gt[6];
+      m7[x] = gt[7];
+      o4[x] = gt[4];
+      const T below = r == 0 ? -(gt[4] + gt[7] + gt[8]) : (r > j0 ? Ua[x] : T(0));
+      Pcur[x] = (below + gt[0]) + kq[r];
+      Ua[x] = gt[2];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+      const T D = (o4[x] + m8[xm]) + m7[xp];
+      if (r > j0)
+        rq[(size_t)(r - 1) * c.P + x] = Pprev[x] + D;
+      else if (r > 0)
+        ed[(size_t)b * c.P + x] = D;
+      const T P = (Pcur[x] + m1[xm]) + m3[xp];
+      const T U = (Ua[x] + m5[xm]) + m6[xp];
+      Pcur[x] = P;
+      Ua[x] = U;
+      if (r == j1 - 1) {
+        rq[(size_t)r * c.P + x] = r == ny - 1 ? P + D : P;
+        if (r < ny - 1) eu[(size_t)b * c.P + x] = U;
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <typename T, typename C, bool PULL, bool EMIT>
-__global__ void __launch_bounds__(256) k_collide(Consts c, const T* __restrict__ Fin, const T* __restrict__ Gin,
-                                                 T* __restrict__ Fout, T* __restrict__ Gout,
-                                                 const T* __restrict__ phi, const T* __restrict__ rows,
-                                                 const double* __restrict__ rowsd, double* __restrict__ mom) {
-  // tiles in dispatch order: neighbouring tiles in x run on different XCDs
-  // at the same time and share the lines of their shifted pulls through the
-  // Infinity Cache (measured faster than giving each XCD a contiguous band)
-  const int nbx = (c.nx + blockDim.x - 1) / blockDim.x;
-  const int t = blockIdx.x;
-  collide_body<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, t % nbx, t / nbx);
+__global__ void __launch_bounds__(1024) k_collide(Consts c, const T* __restrict__ Fin, const T* __restrict__ Gin,
+                                                  T* __restrict__ Fout, T* __restrict__ Gout,
+                                                  const T* __restrict__ phi, const T* __restrict__ rows,
+                                                  const double* __restrict__ rowsd, double* __restrict__ mom,
+                                                  T* __restrict__ rq, T* __restrict__ eu, T* __restrict__ ed) {
+  collide_tile<T, C, PULL, EMIT>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, mom, rq, eu, ed, blockIdx.x);
 }
 
 // ------------------------------------------------------------ init kernels
@@ -1354,8 +1447,9 @@ __global__ void __launch_bounds__(512) kb_forward(const SlotDesc* __restrict__ D
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
-  forward_body<T, 0>(d.c, (const T*)d.b.g[d.cur], (const T*)d.b.rows, nullptr, d.plan, (const C2<T>*)d.b.tw,
-                     (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny, blockIdx.x - off[s]);
+  const ChargeSrc<T> q{(const T*)d.b.rq, (const T*)d.b.eu, (const T*)d.b.ed, nullptr, nullptr};
+  forward_body<T, 0>(d.c, q, d.plan, (const C2<T>*)d.b.tw, (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny,
+                     blockIdx.x - off[s]);
 }
 
 template <typename T>
@@ -1401,19 +1495,22 @@ __global__ void __launch_bounds__(512) kb_inverse(const SlotDesc* __restrict__ D
 }
 
 template <typename T, typename C>
-__global__ void __launch_bounds__(256) kb_collide(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
-  const int b = blockIdx.x;
-  const int s = find_slot(off, ns, b);
+__global__ void __launch_bounds__(1024) kb_collide(const SlotDesc* __restrict__ D, const int* __restrict__ off,
+                                                   int ns) {
+  const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
-  const int lb = b - off[s];
-  const int nbx = (d.c.nx + blockDim.x - 1) / blockDim.x;
   const int src = d.cur, dst = 1 - d.cur;
-  collide_body<T, C, true>(d.c, (const T*)d.b.f[src], (const T*)d.b.g[src], (T*)d.b.f[dst], (T*)d.b.g[dst],
-                           (const T*)d.b.phi, (const T*)d.b.rows, d.b.rowsd, slot_emits(d) ? d.b.mom : nullptr,
-                           lb % nbx, lb / nbx);
+  const int b = blockIdx.x - off[s];
+  if (slot_emits(d))
+    collide_tile<T, C, true, true>(d.c, (const T*)d.b.f[src], (const T*)d.b.g[src], (T*)d.b.f[dst],
+                                   (T*)d.b.g[dst], (const T*)d.b.phi, (const T*)d.b.rows, d.b.rowsd, d.b.mom,
+                                   (T*)d.b.rq, (T*)d.b.eu, (T*)d.b.ed, b);
+  else
+    collide_tile<T, C, true, false>(d.c, (const T*)d.b.f[src], (const T*)d.b.g[src], (T*)d.b.f[dst],
+                                    (T*)d.b.g[dst], (const T*)d.b.phi, (const T*)d.b.rows, d.b.rowsd, d.b.mom,
+                                    (T*)d.b.rq, (T*)d.b.eu, (T*)d.b.ed, b);
 }
-
 // Diagnostics of the slots that emitted moments this step (one block each):
 // rms u_y, max |u| and the total charge, into the slot's history.
 __global__ void __launch_bounds__(256) kb_stats(SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
@@ -1473,7 +1570,7 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu) {
     case BK_TRI_REDUCED:
       if (nm <= 0 || c.NC < 2) return 0;
       return c.NC - 1 <= kScanMax ? (nm + 3) / 4 : (nm + 255) / 256;
-    case BK_COLLIDE: return ((c.nx + tu.cbx - 1) / tu.cbx) * ((c.ny + tu.cby - 1) / tu.cby);
+    case BK_COLLIDE: return collide_tiles(c);
     case BK_STATS: return 1;
   }
   return 0;
@@ -1481,7 +1578,7 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu) {
 
 template <typename T, typename C>
 hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
-                             const Tuning& tu, hipStream_t s) {
+                             size_t collide_lds, const Tuning& tu, hipStream_t s) {
   const int row = ns + 1;
   SlotDesc* D = const_cast<SlotDesc*>(d_desc);
   if (totals[BK_FORWARD])
@@ -1495,7 +1592,7 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
   if (totals[BK_INVERSE])
     hipLaunchKernelGGL(kb_inverse<T>, dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s, d_desc, d_off + BK_INVERSE * row, ns);
   if (totals[BK_COLLIDE])
-    hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(tu.cbx, tu.cby), 0, s, d_desc,
+    hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(tu.cbx * tu.cby), collide_lds, s, d_desc,
                        d_off + BK_COLLIDE * row, ns);
   if (totals[BK_STATS])
     hipLaunchKernelGGL(kb_stats, dim3(totals[BK_STATS]), dim3(256), 0, s, D, d_off + BK_STATS * row, ns);
@@ -1503,11 +1600,11 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
   return hipGetLastError();
 }
 
-template hipError_t launch_batch_step<double, double>(const SlotDesc*, const int*, const int*, int, size_t,
+template hipError_t launch_batch_step<double, double>(const SlotDesc*, const int*, const int*, int, size_t, size_t,
                                                      const Tuning&, hipStream_t);
-template hipError_t launch_batch_step<float, float>(const SlotDesc*, const int*, const int*, int, size_t,
+template hipError_t launch_batch_step<float, float>(const SlotDesc*, const int*, const int*, int, size_t, size_t,
                                                    const Tuning&, hipStream_t);
-template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*, const int*, int, size_t,
+template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*, const int*, int, size_t, size_t,
                                                     const Tuning&, hipStream_t);
 
 // ------------------------------------------------------------- launchers
@@ -1535,18 +1632,17 @@ hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int
                           hipStream_t s) {
   dim3 blk(tu.fft_threads), grd((c.ny + 1) / 2);
   const size_t lds = fft_lds_bytes<T>(pl, tu.fft_threads);
-  const T* G = (const T*)b.g[src];
-  const T* rows = (const T*)b.rows;
-  const double* fld = b.mom + 3 * (size_t)c.ny * c.nx;
+  const ChargeSrc<T> q{(const T*)b.rq, (const T*)b.eu, (const T*)b.ed, (const T*)b.g[src],
+                       b.mom + 3 * (size_t)c.ny * c.nx};
   C2<T>* spec = (C2<T>*)b.spec;
   const C2<T>* tw = (const C2<T>*)b.tw;
   double* dcs = b.rowsd + ROWD_DCSUM * c.ny;
   if (mode == 0)
-    hipLaunchKernelGGL((k_forward<T, 0>), grd, blk, lds, s, c, G, rows, fld, pl, tw, spec, dcs);
+    hipLaunchKernelGGL((k_forward<T, 0>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_forward<T, 1>), grd, blk, lds, s, c, G, rows, fld, pl, tw, spec, dcs);
+    hipLaunchKernelGGL((k_forward<T, 1>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
   else
-    hipLaunchKernelGGL((k_forward<T, 2>), grd, blk, lds, s, c, G, rows, fld, pl, tw, spec, dcs);
+    hipLaunchKernelGGL((k_forward<T, 2>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
   return hipGetLastError();
 }
 
@@ -1579,23 +1675,29 @@ hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, con
 template <typename T, typename C>
 hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst,
                           const Tuning& tu, hipStream_t s) {
-  dim3 blk(tu.cbx, tu.cby);
-  const dim3 g2 = node_grid2(c, blk);
-  dim3 grd(g2.x * g2.y);
+  dim3 blk(tu.cbx * tu.cby), grd(collide_tiles(c));
+  const size_t lds = collide_lds_bytes<T>(c.nx);
   const T* Fin = (const T*)b.f[src];
   const T* Gin = (const T*)b.g[src];
   T* Fout = (T*)b.f[dst];
   T* Gout = (T*)b.g[dst];
   const T* phi = (const T*)b.phi;
   const T* rows = (const T*)b.rows;
+  T* rq = (T*)b.rq;
+  T* eu = (T*)b.eu;
+  T* ed = (T*)b.ed;
   if (pull && emit)
-    hipLaunchKernelGGL((k_collide<T, C, true, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, true, true>), grd, blk, lds, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd,
+                       b.mom, rq, eu, ed);
   else if (pull)
-    hipLaunchKernelGGL((k_collide<T, C, true, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, true, false>), grd, blk, lds, s, c, Fin, Gin, Fout, Gout, phi, rows,
+                       b.rowsd, b.mom, rq, eu, ed);
   else if (emit)
-    hipLaunchKernelGGL((k_collide<T, C, false, true>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, false, true>), grd, blk, lds, s, c, Fin, Gin, Fout, Gout, phi, rows,
+                       b.rowsd, b.mom, rq, eu, ed);
   else
-    hipLaunchKernelGGL((k_collide<T, C, false, false>), grd, blk, 0, s, c, Fin, Gin, Fout, Gout, phi, rows, b.rowsd, b.mom);
+    hipLaunchKernelGGL((k_collide<T, C, false, false>), grd, blk, lds, s, c, Fin, Gin, Fout, Gout, phi, rows,
+                       b.rowsd, b.mom, rq, eu, ed);
   return hipGetLastError();
 }
 

@@ -213,7 +213,7 @@ class Simulation:
                  "q_collector"]
         return dict(zip(names, list(buf))), code == OK
 
-    def set_tuning(self, fft_threads=256, collide_bx=64, collide_by=4):
+    def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
 
     def save(self) -> torch.Tensor:
@@ -325,7 +325,7 @@ class Batch:
         _check(lib().lbm_ec_batch_history(self._h, int(slot), buf, self.hist_rows))
         return np.frombuffer(buf, dtype=np.float64).reshape(self.hist_rows, 4).copy()
 
-    def set_tuning(self, fft_threads=256, collide_bx=64, collide_by=4):
+    def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_batch_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
 
     def release(self, slot):

@@ -41,6 +41,11 @@ def _check(kw, steps, tol, fields=("rho", "u", "rho_c", "phi")):
     (8, 3, 10),
     (1, 16, 40),
     (200, 33, 20),
+    # collide tiles of 2, 4 and 16 rows, full and partial last tiles
+    (8, 520, 30),
+    (6, 1100, 20),
+    (5, 1027, 20),
+    (3, 4200, 10),
 ])
 def test_fp64_small(nx, ny, steps):
     _check(dict(BASE, nx=nx, ny=ny), steps, TOL64)
@@ -71,7 +76,7 @@ def test_fp64_full_122x100_2000_steps():
 
 
 @pytest.mark.parametrize("precision", ["fp32_f64math", "fp32"])
-@pytest.mark.parametrize("nx,ny,steps", [(16, 12, 50), (122, 100, 200), (61, 40, 300)])
+@pytest.mark.parametrize("nx,ny,steps", [(16, 12, 50), (122, 100, 200), (61, 40, 300), (7, 1027, 40)])
 def test_fp32_storage_small(nx, ny, steps, precision):
     _check(dict(BASE, nx=nx, ny=ny, precision=precision), steps, TOL32)
 
@@ -109,3 +114,23 @@ def test_determinism_bitwise():
     b = gpu_fields(kw, 30)
     for k in ("rho", "ux", "uy", "rho_c", "phi"):
         assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_f64math"])
+def test_launch_shapes_do_not_change_results(precision):
+    """Threads per transform block and per collide tile are free to tune:
+    the fields are bitwise the same (ny = 600 gives two-row collide tiles)."""
+    from paper_1812_05711_amd.lbm_ec import Simulation
+    import torch
+
+    out = []
+    for tu in ((128, 64, 1), (512, 1024, 1), (256, 128, 2)):
+        sim = Simulation(device="cuda:0", precision=precision, **dict(BASE, nx=100, ny=600))
+        sim.set_tuning(*tu)
+        sim.step(15)
+        f = sim.fields()
+        torch.cuda.synchronize()
+        out.append({k: v.cpu().numpy() for k, v in f.items()})
+        sim.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]) and np.array_equal(out[0][k], out[2][k]), k
