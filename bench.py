@@ -45,7 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COLLIDE_BYTES_PER_NODE = {"fp32": 148, "fp32_f64math": 148, "fp64": 296}
+COLLIDE_BYTES_PER_NODE = {"fp32": 152, "fp32_f64math": 152, "fp64": 304}
 STEP_BYTES_PER_NODE = {"fp32": 176, "fp32_f64math": 176, "fp64": 352}
 WORKLOAD = dict(T=500.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6,
                 noise_amp=1e-4, seed=181205711)

@@ -122,7 +122,7 @@ Layout make_layout(const lbm_ec_params& p) {
   L.off_gh = take(nc * 6 * L.MP * L.tsize);
   L.off_rf = take((size_t)L.MP * ec::RF_COUNT * L.KP * L.tsize);
   L.off_iface = take(nc * 2 * L.MP * 2 * L.tsize);
-  L.off_tw = take(nx * 2 * L.tsize);
+  L.off_tw = take(nx * 4 * L.tsize);
   L.off_rows = take(ec::ROW_COUNT * ny * L.tsize);
   L.off_rowsd = take(ec::ROWD_COUNT * ny * 8);
   L.off_dmean = take((ny + 1) * 8);
@@ -366,12 +366,32 @@ int setup(lbm_ec* h, unsigned char* ws) {
       }
     }
   }
-  // twiddles exp(-2 pi i k / nx)
-  std::vector<T> tw(2 * (size_t)nx);
+  // twiddles exp(-2 pi i k / nx), then the same factors pass-major: for each
+  // pass of radix R in {2, 3, 4, 5, 8} (Ns the product of the earlier
+  // radices) and each k < Ns the R - 1 factors exp(-2 pi i r k / (Ns R)),
+  // r = 1 .. R-1, next to each other (a butterfly reads them contiguously)
+  std::vector<T> tw(4 * (size_t)nx, T(0));
+  const long double twopi = 2.0L * 3.14159265358979323846264338327950288L;
   for (int k = 0; k < nx; ++k) {
-    const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)nx;
+    const long double a = twopi * (long double)k / (long double)nx;
     tw[2 * k] = (T)cosl(a);
     tw[2 * k + 1] = (T)(-sinl(a));
+  }
+  {
+    size_t o = 2 * (size_t)nx;
+    long long Ns = 1;
+    for (int p = 0; p < h->plan.nr; ++p) {
+      const int R = h->plan.r[p];
+      if (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
+        for (long long k = 0; k < Ns; ++k)
+          for (int r = 1; r < R; ++r) {
+            const long double a = twopi * (long double)(r * k) / (long double)(Ns * R);
+            tw[o++] = (T)cosl(a);
+            tw[o++] = (T)(-sinl(a));
+          }
+      }
+      Ns *= R;
+    }
   }
   EC_HIP(hipMemcpyAsync(h->b.rows, rows.data(), rows.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.rowsd, rowsd.data(), rowsd.size() * sizeof(double), hipMemcpyHostToDevice, h->s));

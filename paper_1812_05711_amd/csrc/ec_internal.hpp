@@ -21,13 +21,14 @@ struct FftPlan {
 // into registers, the block synchronises, the outputs overwrite the buffer)
 // when every radix has a register butterfly and a pass gives each thread at
 // most kFftPerThread elements; otherwise they ping-pong between two buffers.
+// (Kernels built for fewer elements per thread need fewer registers.)
 constexpr int kFftPerThread = 16;
-__host__ __device__ inline bool fft_in_place(const FftPlan& pl, int threads) {
+__host__ __device__ inline bool fft_in_place(const FftPlan& pl, int threads, int per_thread = kFftPerThread) {
   for (int p = 0; p < pl.nr; ++p) {
     const int r = pl.r[p];
     if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return false;
   }
-  return pl.n <= kFftPerThread * threads;
+  return pl.n <= per_thread * threads;
 }
 
 // Rows per collide tile, a function of the grid alone: the tile edges fix
@@ -124,7 +125,7 @@ struct Bufs {
   void* ed;      // [tiles][P] contribution of each tile's first row to the row below it
   void* iface;   // [P][2][MP] complex: interface values a_k (last row of chunk k),
                  //                      b_k (first row of chunk k+1)
-  void* tw;      // [nx] complex twiddles exp(-2 pi i k / nx)
+  void* tw;      // [nx] complex twiddles exp(-2 pi i k / nx), then [<= nx] pass-major ones
   void* rows;    // ROW_COUNT x [ny]
   double* rowsd; // ROWD_COUNT x [ny]
   double* dmean; // [ny + 1] x-mean row differences D(-1) .. D(ny-1)

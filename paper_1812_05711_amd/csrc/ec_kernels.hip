@@ -118,22 +118,18 @@ __device__ __forceinline__ void dft8(C2<T>* v) {
 // earlier passes; the last pass leaves natural order.
 template <typename T, bool INV, int R>
 __device__ __forceinline__ void stockham_pass(const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
-                                              int N, int Ns, const C2<T>* __restrict__ tw) {
+                                              int N, int Ns, const C2<T>* __restrict__ twp) {
   const int stride = N / R;
-  const int twstep = N / (Ns * R);
   for (int t = threadIdx.x; t < stride; t += blockDim.x) {
     const int k = t % Ns;
-    const int e = k * twstep;
+    const C2<T>* tk = twp + k * (R - 1);
     C2<T> v[R];
     v[0] = src[t];
-    int idx = e;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      C2<T> w = tw[idx];
+      C2<T> w = tk[r - 1];
       if (INV) w.im = -w.im;
       v[r] = cmul(src[t + r * stride], w);
-      idx += e;
-      if (idx >= N) idx -= N;
     }
     if constexpr (R == 2) dft2<T, INV>(v);
     if constexpr (R == 3) dft3<T, INV>(v);
@@ -177,19 +173,21 @@ __device__ __forceinline__ void generic_pass(const C2<T>* __restrict__ src, C2<T
 template <typename T, bool INV>
 __device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftPlan& pl, const C2<T>* __restrict__ tw) {
   const int N = pl.n;
-  int Ns = 1;
+  int Ns = 1, off = 0;
+  const C2<T>* twp = tw + N;  // pass-major twiddles follow the full table
   C2<T>* src = a;
   C2<T>* dst = b;
   for (int p = 0; p < pl.nr; ++p) {
     const int R = pl.r[p];
     switch (R) {
-      case 2: stockham_pass<T, INV, 2>(src, dst, N, Ns, tw); break;
-      case 3: stockham_pass<T, INV, 3>(src, dst, N, Ns, tw); break;
-      case 4: stockham_pass<T, INV, 4>(src, dst, N, Ns, tw); break;
-      case 5: stockham_pass<T, INV, 5>(src, dst, N, Ns, tw); break;
-      case 8: stockham_pass<T, INV, 8>(src, dst, N, Ns, tw); break;
+      case 2: stockham_pass<T, INV, 2>(src, dst, N, Ns, twp + off); break;
+      case 3: stockham_pass<T, INV, 3>(src, dst, N, Ns, twp + off); break;
+      case 4: stockham_pass<T, INV, 4>(src, dst, N, Ns, twp + off); break;
+      case 5: stockham_pass<T, INV, 5>(src, dst, N, Ns, twp + off); break;
+      case 8: stockham_pass<T, INV, 8>(src, dst, N, Ns, twp + off); break;
       default: generic_pass<T, INV>(src, dst, N, Ns, R, tw); break;
     }
+    if (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) off += Ns * (R - 1);
     __syncthreads();
     C2<T>* tmp = src;
     src = dst;
@@ -203,25 +201,21 @@ __device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftPlan& pl, const C2<T>* __
 // butterflies of the pass in registers between the read and the write phase.
 template <typename T, bool INV, int R, int NB>
 __device__ __forceinline__ void stockham_pass_ip(C2<T>* __restrict__ buf, int N, int Ns,
-                                                 const C2<T>* __restrict__ tw) {
+                                                 const C2<T>* __restrict__ twp) {
   const int stride = N / R;
-  const int twstep = N / (Ns * R);
   C2<T> v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int t = threadIdx.x + q * blockDim.x;
     if (t < stride) {
       const int k = t % Ns;
-      const int e = k * twstep;
+      const C2<T>* tk = twp + k * (R - 1);
       v[q][0] = buf[t];
-      int idx = e;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        C2<T> w = tw[idx];
+        C2<T> w = tk[r - 1];
         if (INV) w.im = -w.im;
         v[q][r] = cmul(buf[t + r * stride], w);
-        idx += e;
-        if (idx >= N) idx -= N;
       }
       if constexpr (R == 2) dft2<T, INV>(v[q]);
       if constexpr (R == 3) dft3<T, INV>(v[q]);
@@ -244,21 +238,22 @@ __device__ __forceinline__ void stockham_pass_ip(C2<T>* __restrict__ buf, int N,
 }
 
 // The same transform as fft_lds, in place in buffer a (requires
-// fft_in_place(pl, blockDim.x)).
-template <typename T, bool INV>
+// fft_in_place(pl, blockDim.x, F)).
+template <typename T, bool INV, int F>
 __device__ C2<T>* fft_lds_ip(C2<T>* a, const FftPlan& pl, const C2<T>* __restrict__ tw) {
-  constexpr int F = kFftPerThread;
   const int N = pl.n;
   int Ns = 1;
+  const C2<T>* twp = tw + N;
   for (int p = 0; p < pl.nr; ++p) {
     const int R = pl.r[p];
     switch (R) {
-      case 2: stockham_pass_ip<T, INV, 2, (F + 1) / 2>(a, N, Ns, tw); break;
-      case 3: stockham_pass_ip<T, INV, 3, (F + 2) / 3>(a, N, Ns, tw); break;
-      case 4: stockham_pass_ip<T, INV, 4, (F + 3) / 4>(a, N, Ns, tw); break;
-      case 5: stockham_pass_ip<T, INV, 5, (F + 4) / 5>(a, N, Ns, tw); break;
-      default: stockham_pass_ip<T, INV, 8, (F + 7) / 8>(a, N, Ns, tw); break;
+      case 2: stockham_pass_ip<T, INV, 2, (F + 1) / 2>(a, N, Ns, twp); break;
+      case 3: stockham_pass_ip<T, INV, 3, (F + 2) / 3>(a, N, Ns, twp); break;
+      case 4: stockham_pass_ip<T, INV, 4, (F + 3) / 4>(a, N, Ns, twp); break;
+      case 5: stockham_pass_ip<T, INV, 5, (F + 4) / 5>(a, N, Ns, twp); break;
+      default: stockham_pass_ip<T, INV, 8, (F + 7) / 8>(a, N, Ns, twp); break;
     }
+    twp += Ns * (R - 1);
     __syncthreads();
     Ns *= R;
   }
@@ -455,7 +450,7 @@ __device__ __forceinline__ void row_sums_fixed_order(const C2<T>* __restrict__ a
 // imaginary parts of one complex transform.  Writes the source spectrum
 // s_m = -DFT(rho_c - r)_m / eps for m = 1 .. nx/2 (Eq. 4, 19) and the FP64
 // row sums of the charge deviation (the m = 0 mode).
-template <typename T, int MODE>
+template <typename T, int MODE, int F>
 __device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>& q, const FftPlan& pl,
                                              const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
                                              double* __restrict__ dcsum, int bx) {
@@ -463,7 +458,7 @@ __device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>
   C2<T>* a = reinterpret_cast<C2<T>*>(smem);
   C2<T>* b = a + pl.n;  // second transform buffer, or only the scratch when in place
   double* red = reinterpret_cast<double*>(b);  // idle until the transform
-  const bool ip = fft_in_place(pl, blockDim.x);
+  const bool ip = fft_in_place(pl, blockDim.x, F);
   const int j0 = 2 * bx, j1 = j0 + 1;
   const bool has1 = j1 < c.ny;
   const int j1c = has1 ? j1 : j0;  // a missing second row re-reads the first; dropped below
@@ -494,7 +489,7 @@ __device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>
     if (has1) dcsum[j1] = s1;
   }
   __syncthreads();
-  C2<T>* z = ip ? fft_lds_ip<T, false>(a, pl, tw) : fft_lds<T, false>(a, b, pl, tw);
+  C2<T>* z = ip ? fft_lds_ip<T, false, F>(a, pl, tw) : fft_lds<T, false>(a, b, pl, tw);
   const T sc = T(-0.5 / c.eps);
   const int N = pl.n;
   for (int m = threadIdx.x; m < c.M; m += blockDim.x) {
@@ -510,10 +505,10 @@ __device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int F>
 __global__ void __launch_bounds__(512) k_forward(Consts c, ChargeSrc<T> q, FftPlan pl, const C2<T>* __restrict__ tw,
                                                  C2<T>* __restrict__ spec, double* __restrict__ dcsum) {
-  forward_body<T, MODE>(c, q, pl, tw, spec, dcsum, blockIdx.x);
+  forward_body<T, MODE, F>(c, q, pl, tw, spec, dcsum, blockIdx.x);
 }
 
 // --------------------------------------------------- x-mean mode (m = 0)
@@ -675,14 +670,21 @@ __device__ __forceinline__ void tri_local_body(const Consts& c, const T* __restr
   const int len = min(kChunk, c.ny - s0);
   const int type = chunk_type(k, c.NC);
   const size_t MP = c.MP;
+  // every row of the chunk is loaded before the elimination starts (row
+  // index clamped: a short last chunk re-reads its last row, unused)
   C2<T> d[kChunk];
+  T f[kChunk];
+#pragma unroll
+  for (int i = 0; i < kChunk; ++i) {
+    const int ii = min(i, len - 1);
+    d[i] = spec[(size_t)(s0 + ii) * MP + m];
+    f[i] = ttab(tt, c.MP, type, 0, ii, m);
+  }
   C2<T> prev = {T(0), T(0)};
 #pragma unroll
   for (int i = 0; i < kChunk; ++i) {
     if (i < len) {
-      const T f = ttab(tt, c.MP, type, 0, i, m);
-      const C2<T> sv = spec[(s0 + i) * MP + m];
-      prev = C2<T>{(sv.re - prev.re) * f, (sv.im - prev.im) * f};
+      prev = C2<T>{(d[i].re - prev.re) * f[i], (d[i].im - prev.im) * f[i]};
       d[i] = prev;
     }
   }
@@ -694,10 +696,9 @@ __device__ __forceinline__ void tri_local_body(const Consts& c, const T* __restr
         x = d[i];
         last = x;
       } else {
-        const T f = ttab(tt, c.MP, type, 0, i, m);
-        x = C2<T>{d[i].re - f * x.re, d[i].im - f * x.im};
+        x = C2<T>{d[i].re - f[i] * x.re, d[i].im - f[i] * x.im};
       }
-      spec[(s0 + i) * MP + m] = x;
+      spec[(size_t)(s0 + i) * MP + m] = x;
     }
   }
   first = x;
@@ -836,12 +837,21 @@ __device__ __forceinline__ void tri_scan_body(const Consts& c, const T* __restri
   const size_t MP = c.MP;
   const T* f = rf + (size_t)m * RF_COUNT * c.KP;
   const int k0 = lane * E;
+  // all loads first (interface index clamped; unused beyond K)
   C2<T> ye[E], ys[E], H0[E], H1[E];
+  T inv[E], ib[E], A[E], P[E], Q[E], Cf[E], g[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = min(k0 + e, K - 1);
     ye[e] = ends[(2 * (size_t)k + 1) * MP + m];
     ys[e] = ends[(2 * (size_t)(k + 1)) * MP + m];
+    inv[e] = f[RF_INV * c.KP + k];
+    ib[e] = f[RF_IB * c.KP + k];
+    A[e] = f[RF_A * c.KP + k];
+    P[e] = f[RF_P * c.KP + k];
+    Q[e] = f[RF_Q * c.KP + k];
+    Cf[e] = f[RF_C * c.KP + k];
+    g[e] = f[RF_G * c.KP + k];
   }
   // forward: compose this lane's maps h -> A h + B
   T Al = T(1);
@@ -850,10 +860,9 @@ __device__ __forceinline__ void tri_scan_body(const Consts& c, const T* __restri
   for (int e = 0; e < E; ++e) {
     const int k = k0 + e;
     if (k < K) {
-      const T inv = f[RF_INV * c.KP + k], ib = f[RF_IB * c.KP + k], A = f[RF_A * c.KP + k];
-      const C2<T> B = {inv * ye[e].re - ib * ys[e].re, inv * ye[e].im - ib * ys[e].im};
-      Bl = C2<T>{A * Bl.re + B.re, A * Bl.im + B.im};
-      Al = A * Al;
+      const C2<T> B = {inv[e] * ye[e].re - ib[e] * ys[e].re, inv[e] * ye[e].im - ib[e] * ys[e].im};
+      Bl = C2<T>{A[e] * Bl.re + B.re, A[e] * Bl.im + B.im};
+      Al = A[e] * Al;
     }
   }
 #pragma unroll
@@ -871,11 +880,10 @@ __device__ __forceinline__ void tri_scan_body(const Consts& c, const T* __restri
   for (int e = 0; e < E; ++e) {
     const int k = k0 + e;
     if (k < K) {
-      const T inv = f[RF_INV * c.KP + k], ib = f[RF_IB * c.KP + k], A = f[RF_A * c.KP + k];
-      const T P = f[RF_P * c.KP + k], Q = f[RF_Q * c.KP + k];
-      H1[e] = C2<T>{inv * ys[e].re + P * ye[e].re + Q * hp.re, inv * ys[e].im + P * ye[e].im + Q * hp.im};
-      const C2<T> B = {inv * ye[e].re - ib * ys[e].re, inv * ye[e].im - ib * ys[e].im};
-      hp = C2<T>{A * hp.re + B.re, A * hp.im + B.im};
+      H1[e] = C2<T>{inv[e] * ys[e].re + P[e] * ye[e].re + Q[e] * hp.re,
+                    inv[e] * ys[e].im + P[e] * ye[e].im + Q[e] * hp.im};
+      const C2<T> B = {inv[e] * ye[e].re - ib[e] * ys[e].re, inv[e] * ye[e].im - ib[e] * ys[e].im};
+      hp = C2<T>{A[e] * hp.re + B.re, A[e] * hp.im + B.im};
       H0[e] = hp;
     }
   }
@@ -886,9 +894,8 @@ __device__ __forceinline__ void tri_scan_body(const Consts& c, const T* __restri
   for (int e = E - 1; e >= 0; --e) {
     const int k = k0 + e;
     if (k < K) {
-      const T C = f[RF_C * c.KP + k];
-      Dl = C2<T>{C * Dl.re + H1[e].re, C * Dl.im + H1[e].im};
-      Cl = C * Cl;
+      Dl = C2<T>{Cf[e] * Dl.re + H1[e].re, Cf[e] * Dl.im + H1[e].im};
+      Cl = Cf[e] * Cl;
     }
   }
 #pragma unroll
@@ -906,9 +913,8 @@ __device__ __forceinline__ void tri_scan_body(const Consts& c, const T* __restri
   for (int e = E - 1; e >= 0; --e) {
     const int k = k0 + e;
     if (k < K) {
-      const T C = f[RF_C * c.KP + k], g = f[RF_G * c.KP + k];
-      const C2<T> a = {H0[e].re - g * bn.re, H0[e].im - g * bn.im};
-      const C2<T> b = {H1[e].re + C * bn.re, H1[e].im + C * bn.im};
+      const C2<T> a = {H0[e].re - g[e] * bn.re, H0[e].im - g[e] * bn.im};
+      const C2<T> b = {H1[e].re + Cf[e] * bn.re, H1[e].im + Cf[e] * bn.im};
       iface[(2 * (size_t)k) * MP + m] = a;
       iface[(2 * (size_t)k + 1) * MP + m] = b;
       bn = b;
@@ -990,7 +996,7 @@ __device__ __forceinline__ void inverse_gather(const Consts& c, const C2<T>* __r
 // Pair of rows per block: Z_m = X_m + i Y_m with the Hermitian halves of the
 // two solved spectra (m = 0 left out: it lives in the x-mean row), inverse
 // transform, 1/nx, real / imaginary parts to the two rows of phi.
-template <typename T>
+template <typename T, int F>
 __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __restrict__ spec,
                                              const T* __restrict__ tt, const C2<T>* __restrict__ iface,
                                              const FftPlan& pl, const C2<T>* __restrict__ tw, T* __restrict__ phi,
@@ -1012,7 +1018,7 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
   else
     inverse_gather<T, false, false>(c, spec, tt, iface, j0, has1, N, a);
   __syncthreads();
-  C2<T>* z = fft_in_place(pl, blockDim.x) ? fft_lds_ip<T, true>(a, pl, tw) : fft_lds<T, true>(a, b, pl, tw);
+  C2<T>* z = fft_in_place(pl, blockDim.x, F) ? fft_lds_ip<T, true, F>(a, pl, tw) : fft_lds<T, true>(a, b, pl, tw);
   const T inv = T(1.0 / (double)N);
   for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
     phi[(size_t)j0 * c.P + x] = z[x].re * inv;
@@ -1020,11 +1026,11 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
   }
 }
 
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(512) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
                                                  const C2<T>* __restrict__ iface, FftPlan pl,
                                                  const C2<T>* __restrict__ tw, T* __restrict__ phi) {
-  inverse_body<T>(c, spec, tt, iface, pl, tw, phi, blockIdx.x);
+  inverse_body<T, F>(c, spec, tt, iface, pl, tw, phi, blockIdx.x);
 }
 
 // ------------------------------------------- fused collide (and stream)
@@ -1448,7 +1454,7 @@ __global__ void __launch_bounds__(512) kb_forward(const SlotDesc* __restrict__ D
   const SlotDesc& d = D[s];
   if (!d.active) return;
   const ChargeSrc<T> q{(const T*)d.b.rq, (const T*)d.b.eu, (const T*)d.b.ed, nullptr, nullptr};
-  forward_body<T, 0>(d.c, q, d.plan, (const C2<T>*)d.b.tw, (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny,
+  forward_body<T, 0, kFftPerThread>(d.c, q, d.plan, (const C2<T>*)d.b.tw, (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny,
                      blockIdx.x - off[s]);
 }
 
@@ -1490,7 +1496,7 @@ __global__ void __launch_bounds__(512) kb_inverse(const SlotDesc* __restrict__ D
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
-  inverse_body<T>(d.c, (const C2<T>*)d.b.spec, (const T*)d.b.tt, (const C2<T>*)d.b.iface, d.plan,
+  inverse_body<T, kFftPerThread>(d.c, (const C2<T>*)d.b.spec, (const T*)d.b.tt, (const C2<T>*)d.b.iface, d.plan,
                   (const C2<T>*)d.b.tw, (T*)d.b.phi, blockIdx.x - off[s]);
 }
 
@@ -1637,12 +1643,15 @@ hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int
   C2<T>* spec = (C2<T>*)b.spec;
   const C2<T>* tw = (const C2<T>*)b.tw;
   double* dcs = b.rowsd + ROWD_DCSUM * c.ny;
-  if (mode == 0)
-    hipLaunchKernelGGL((k_forward<T, 0>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
+  const bool f8 = fft_in_place(pl, tu.fft_threads, 8);
+  if (mode == 0 && f8)
+    hipLaunchKernelGGL((k_forward<T, 0, 8>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_forward<T, 0, kFftPerThread>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_forward<T, 1>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
+    hipLaunchKernelGGL((k_forward<T, 1, kFftPerThread>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
   else
-    hipLaunchKernelGGL((k_forward<T, 2>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
+    hipLaunchKernelGGL((k_forward<T, 2, kFftPerThread>), grd, blk, lds, s, c, q, pl, tw, spec, dcs);
   return hipGetLastError();
 }
 
@@ -1667,8 +1676,12 @@ template <typename T>
 hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, const Tuning& tu, hipStream_t s) {
   dim3 blk(tu.fft_threads), grd((c.ny + 1) / 2);
   const size_t lds = fft_lds_bytes<T>(pl, tu.fft_threads);
-  hipLaunchKernelGGL(k_inverse<T>, grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
-                     (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
+  if (fft_in_place(pl, tu.fft_threads, 8))
+    hipLaunchKernelGGL((k_inverse<T, 8>), grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
+                       (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
+  else
+    hipLaunchKernelGGL((k_inverse<T, kFftPerThread>), grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
+                       (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
   return hipGetLastError();
 }
 
