@@ -64,19 +64,23 @@ def kernel_source_hash():
 
 
 def traffic_from_profiles(nx, ny, precision):
-    """HBM bytes per collide launch from the committed counter summary, if it
-    was taken on the current kernel source and the same workload."""
-    path = os.path.join(ROOT, "profiles", "collide_traffic.json")
+    """HBM bytes per collide launch from the committed counter summary
+    (profiles/collide_<nx>x<ny>_<precision>_hbm_counters.md), if it was taken
+    on the current kernel source and the same workload; else None."""
+    path = os.path.join(ROOT, "profiles", f"collide_{nx}x{ny}_{precision}_hbm_counters.md")
     if not os.path.exists(path):
         return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", " ")):
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
     try:
-        t = json.load(open(path))
-    except Exception:
+        ok = (vals.get("source_hash") == kernel_source_hash() and int(vals.get("nx", -1)) == nx
+              and int(vals.get("ny", -1)) == ny and vals.get("precision") == precision)
+        return float(vals["traffic_bytes_per_launch"]) if ok else None
+    except (KeyError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash() or t.get("nx") != nx or t.get("ny") != ny \
-            or t.get("precision") != precision:
-        return None
-    return t.get("hbm_bytes_per_launch")
 
 
 CPU_SNIPPET = r"""

@@ -197,7 +197,9 @@ int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 /* Launch shapes, which never change results: threads per x-transform block
  * (64, 128, 256 or 512) and threads per collide tile (collide_bx *
  * collide_by, a multiple of 64 up to 1024; a tile is a band of whole rows
- * whose height depends on ny only).  Defaults 256 and 256 x 1.  Applies to
+ * whose height depends on ny only).  Defaults: about nx / 8 transform
+ * threads (64 .. 512) and nx rounded up to 64 collide threads (at most 1024)
+ * for a single instance; 256 and 256 x 1 for a batch.  Applies to
  * the following steps; EINVAL for other values.  The autotuner in
  * paper_1812_05711_amd/autotune.py picks them by timing. */
 int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by);

@@ -1,5 +1,6 @@
 // Host side of the library: parameter mapping, reference rows, transform
 // plans, workspace layout, the time loop and the C ABI of include/lbm_ec.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -76,6 +77,18 @@ ec::FftPlan make_plan(int n) {
       m /= q;
     }
   return p;
+}
+
+// Launch shapes of a new instance: whole rows of collide threads (up to
+// 1024) and about eight transform elements per thread (64 .. 512).
+ec::Tuning default_tuning(int nx) {
+  ec::Tuning tu;
+  const int r64 = (nx + 63) / 64 * 64;
+  tu.cbx = std::min(1024, std::max(64, r64));
+  tu.cby = 1;
+  const int f = ((nx + 7) / 8 + 63) / 64 * 64;
+  tu.fft_threads = f <= 64 ? 64 : (f <= 128 ? 128 : (f <= 256 ? 256 : 512));
+  return tu;
 }
 
 struct Layout {
@@ -477,6 +490,7 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
   h->s = s;
   h->fp32 = p->precision != LBM_EC_FP64;
   h->plan = make_plan(p->nx);
+  h->tu = default_tuning(p->nx);
   h->b.f[0] = ws + L.off_f[0];
   h->b.f[1] = ws + L.off_f[1];
   h->b.g[0] = ws + L.off_g[0];
@@ -967,6 +981,7 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
   h->s = (hipStream_t)hip_stream;
   h->fp32 = p->precision != LBM_EC_FP64;
   h->plan = make_plan(p->nx);
+  h->tu = default_tuning(p->nx);
   unsigned char* ws = (unsigned char*)d_ws;
   h->b.f[0] = ws + L.off_f[0];
   h->b.f[1] = ws + L.off_f[1];
