@@ -96,7 +96,7 @@ struct Layout {
   size_t tsize;
   size_t off_f[2], off_g[2], off_phi, off_rq, off_eu, off_ed, off_spec, off_tt, off_ends, off_gh, off_rf, off_iface,
       off_tw, off_rows,
-      off_rowsd, off_dmean, off_mom, off_stats, total;
+      off_rowsd, off_dmean, off_mom, off_stats, off_spart, total;
 };
 
 Layout make_layout(const lbm_ec_params& p) {
@@ -141,6 +141,7 @@ Layout make_layout(const lbm_ec_params& p) {
   L.off_dmean = take((ny + 1) * 8);
   L.off_mom = take(4 * ny * nx * 8);
   L.off_stats = take(16 * 8);
+  L.off_spart = take((size_t)ec::kStatsBands * 8 * 8);
   L.total = o;
   return L;
 }
@@ -511,6 +512,7 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
   h->b.dmean = (double*)(ws + L.off_dmean);
   h->b.mom = (double*)(ws + L.off_mom);
   h->b.stats = (double*)(ws + L.off_stats);
+  h->b.spart = (double*)(ws + L.off_spart);
   int rc = h->fp32 ? setup<float>(h, ws) : setup<double>(h, ws);
   if (!rc) {
     if (p->precision == LBM_EC_FP64)
@@ -1003,6 +1005,7 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
   h->b.dmean = (double*)(ws + L.off_dmean);
   h->b.mom = (double*)(ws + L.off_mom);
   h->b.stats = (double*)(ws + L.off_stats);
+  h->b.spart = (double*)(ws + L.off_spart);
   rc = h->fp32 ? setup<float>(h, ws) : setup<double>(h, ws);
   if (!rc) {
     if (p->precision == LBM_EC_FP64)

@@ -36,6 +36,9 @@ __host__ __device__ inline bool fft_in_place(const FftPlan& pl, int threads, int
 // shape must not move them.
 __host__ __device__ inline int tile_rows(int ny) { return ny >= 512 ? (ny / 256 < 16 ? ny / 256 : 16) : 1; }
 
+// Bands of rows reduced by separate blocks in the diagnostics.
+constexpr int kStatsBands = 1024;
+
 // Rows per chunk of the partitioned per-wavenumber solves.
 constexpr int kChunk = 32;
 // Chunk types: the whole column (one chunk), the first one (lower electrode
@@ -131,6 +134,7 @@ struct Bufs {
   double* dmean; // [ny + 1] x-mean row differences D(-1) .. D(ny-1)
   double* mom;   // [4][ny][nx] emitted moments: rho - rho_ref, ux, uy, rho_c - r
   double* stats; // [16]
+  double* spart; // [kStatsBands][8] partial diagnostics of bands of rows
 };
 
 // One slot of a batch: an instance's constants, buffers and transform plan,

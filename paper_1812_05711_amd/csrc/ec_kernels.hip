@@ -1351,19 +1351,74 @@ __global__ void __launch_bounds__(256) k_charge_in(Consts c, const double* __res
   mom[3 * n + k] = rc_nd[k] * c.eps / (c.H * c.H) - rowsd[ROWD_R * c.ny + j];
 }
 
-// Global FP64 diagnostics of the emitted moments (one block, fixed order),
-// and the charge that the next streaming of the post-collision populations
-// G moves across the electrodes (Table I): in through the injector (the
+// Maximum of v over the block (every thread gets it); `red` holds 16
+// doubles of LDS.
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double m = red[0];
+  for (int w = 1; w < nw; ++w) m = fmax(m, red[w]);
+  return m;
+}
+
+// Global FP64 diagnostics of the emitted moments, in two passes with a
+// fixed reduction order: block b of k_stats_part reduces its band of rows
+// into part[b][0..6] (sums of rho - 1, rho_c, u_y^2 and of the unhealthy
+// nodes; maxima of |u|, -rho_c and |E_x|); k_stats_final reduces the bands
+// in order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_stats_part(Consts c, const double* __restrict__ mom,
+                                                    const T* __restrict__ phi, const double* __restrict__ rowsd,
+                                                    double* __restrict__ part) {
+  __shared__ double red[16];
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int j0 = (int)((long long)c.ny * b / nb), j1 = (int)((long long)c.ny * (b + 1) / nb);
+  const size_t n = (size_t)c.ny * c.nx;
+  double s_drho = 0, s_rc = 0, s_uy2 = 0, bad = 0, mx_u = 0, mx_nrc = -1e300, mx_ex = 0;
+  for (int j = j0; j < j1; ++j) {
+    const double r = rowsd[ROWD_R * c.ny + j], rr = rowsd[ROWD_RHO_REF * c.ny + j];
+    for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
+      const size_t k = (size_t)j * c.nx + x;
+      const double drho = mom[k], ux = mom[n + k], uy = mom[2 * n + k];
+      const double rc = r + mom[3 * n + k];
+      const double rho = rr + drho;
+      s_drho += (rho - 1.0);
+      s_rc += rc;
+      s_uy2 += uy * uy;
+      mx_u = fmax(mx_u, sqrt(ux * ux + uy * uy));
+      mx_nrc = fmax(mx_nrc, -rc);
+      if (!(rho > 0.0) || !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(rc)) bad += 1.0;
+      const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+      const double ex = -((double)phi[(size_t)j * c.P + xp] - (double)phi[(size_t)j * c.P + xm]) / 2.0;
+      mx_ex = fmax(mx_ex, fabs(ex));
+    }
+  }
+  double v[7];
+  v[0] = block_sum(s_drho, red);
+  v[1] = block_sum(s_rc, red);
+  v[2] = block_sum(s_uy2, red);
+  v[3] = block_sum(bad, red);
+  v[4] = block_max(mx_u, red);
+  v[5] = block_max(mx_nrc, red);
+  v[6] = block_max(mx_ex, red);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 7; ++q) part[8 * b + q] = v[q];
+}
+
+// The charge that the next streaming of the post-collision populations G
+// moves across the electrodes (Table I): in through the injector (the
 // anti-bounce-back replaces each outgoing g*_i by 2 w_i rho0 - g*_i) and net
 // in through the collector (the incoming populations copy the last row, the
 // outgoing ones leave).  On deviations the reference rows cancel except in
 // the injector constants g_abb = 2 w_i (rho0 - r(0)).
 template <typename T>
-__global__ void __launch_bounds__(1024) k_stats(Consts c, const double* __restrict__ mom, const T* __restrict__ phi,
-                                                const double* __restrict__ rowsd, const T* __restrict__ G,
-                                                double* __restrict__ out) {
-  __shared__ double red[32];
-  const size_t n = (size_t)c.ny * c.nx;
+__global__ void __launch_bounds__(256) k_stats_final(Consts c, const double* __restrict__ part, int nb,
+                                                     const T* __restrict__ G, double* __restrict__ out) {
+  __shared__ double red[16];
   const size_t plane = (size_t)c.ny * c.P, top = (size_t)(c.ny - 1) * c.P;
   double q_in = 0, q_out = 0;
   for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
@@ -1373,55 +1428,23 @@ __global__ void __launch_bounds__(1024) k_stats(Consts c, const double* __restri
              ((double)G[2 * plane + top + x] + (double)G[5 * plane + top + x] + (double)G[6 * plane + top + x]);
   }
   q_in = block_sum(q_in, red);
-  __syncthreads();
   q_out = block_sum(q_out, red);
-  __syncthreads();
-  double s_drho = 0, s_rc = 0, s_uy2 = 0, mx_u = 0, mn_rc = 1e300, bad = 0, mx_ex = 0;
-  for (size_t k = threadIdx.x; k < n; k += blockDim.x) {
-    const int j = (int)(k / c.nx), x = (int)(k % c.nx);
-    const double drho = mom[k], ux = mom[n + k], uy = mom[2 * n + k];
-    const double rc = rowsd[ROWD_R * c.ny + j] + mom[3 * n + k];
-    const double rho = rowsd[ROWD_RHO_REF * c.ny + j] + drho;
-    s_drho += (rho - 1.0);
-    s_rc += rc;
-    s_uy2 += uy * uy;
-    mx_u = fmax(mx_u, sqrt(ux * ux + uy * uy));
-    mn_rc = fmin(mn_rc, rc);
-    if (!(rho > 0.0) || !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(rc)) bad += 1.0;
-    const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
-    const double ex = -((double)phi[(size_t)j * c.P + xp] - (double)phi[(size_t)j * c.P + xm]) / 2.0;
-    mx_ex = fmax(mx_ex, fabs(ex));
+  double v[7] = {0, 0, 0, 0, 0, -1e300, 0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    for (int q = 0; q < 4; ++q) v[q] += part[8 * b + q];
+    for (int q = 4; q < 7; ++q) v[q] = fmax(v[q], part[8 * b + q]);
   }
-  s_drho = block_sum(s_drho, red);
-  __syncthreads();
-  s_rc = block_sum(s_rc, red);
-  __syncthreads();
-  s_uy2 = block_sum(s_uy2, red);
-  __syncthreads();
-  bad = block_sum(bad, red);
-  __syncthreads();
-  // max / min through the same LDS
-  __shared__ double mx[1024], mn[1024], me[1024];
-  mx[threadIdx.x] = mx_u;
-  mn[threadIdx.x] = mn_rc;
-  me[threadIdx.x] = mx_ex;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
-      mn[threadIdx.x] = fmin(mn[threadIdx.x], mn[threadIdx.x + o]);
-      me[threadIdx.x] = fmax(me[threadIdx.x], me[threadIdx.x + o]);
-    }
-    __syncthreads();
-  }
+  for (int q = 0; q < 4; ++q) v[q] = block_sum(v[q], red);
+  for (int q = 4; q < 7; ++q) v[q] = block_max(v[q], red);
   if (threadIdx.x == 0) {
-    out[1] = s_drho;
-    out[2] = s_rc;
-    out[3] = sqrt(s_uy2 / (double)n);
-    out[4] = mx[0];
-    out[5] = mn[0];
-    out[6] = bad;
-    out[7] = me[0];
+    const double n = (double)c.ny * c.nx;
+    out[1] = v[0];
+    out[2] = v[1];
+    out[3] = sqrt(v[2] / n);
+    out[4] = v[4];
+    out[5] = -v[5];
+    out[6] = v[3];
+    out[7] = v[6];
     out[8] = q_in;
     out[9] = q_out;
   }
@@ -1731,8 +1754,10 @@ hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_
 
 template <typename T>
 hipError_t launch_stats(const Consts& c, const Bufs& b, int cur, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats<T>, dim3(1), dim3(1024), 0, s, c, b.mom, (const T*)b.phi, b.rowsd, (const T*)b.g[cur],
-                     b.stats);
+  const int nb = c.ny < kStatsBands ? c.ny : kStatsBands;
+  hipLaunchKernelGGL(k_stats_part<T>, dim3(nb), dim3(256), 0, s, c, b.mom, (const T*)b.phi, b.rowsd, b.spart);
+  hipLaunchKernelGGL(k_stats_final<T>, dim3(1), dim3(256), 0, s, c, (const double*)b.spart, nb,
+                     (const T*)b.g[cur], b.stats);
   return hipGetLastError();
 }
 
