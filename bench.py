@@ -97,11 +97,11 @@ print(json.dumps(dict(seconds=dt, steps={steps})))
 """
 
 
-def cpu_baseline(nx, ny, steps=2):
+def cpu_baseline(nx, ny, steps=3):
     """The oracle on a bounded sample of the workload: the same row length and
-    parameters on a slab of at most 1024 rows (its cost per node does not
+    parameters on a slab of at most 2048 rows (its cost per node does not
     depend on the row count), `steps` timed steps after one untimed."""
-    ny = min(ny, 1024)
+    ny = min(ny, 2048)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     code = CPU_SNIPPET.format(root=ROOT, nx=nx, ny=ny, kw=WORKLOAD, steps=steps)
     log(f"cpu baseline: oracle at {nx}x{ny}, {steps} timed steps, 1 thread")

@@ -573,6 +573,7 @@ struct lbm_ec_batch {
   int totals[ec::BK_COUNT];
   size_t lds;
   size_t collide_lds;
+  bool fft8;
   bool dirty;
   hipGraphExec_t g_many, g_one;
   bool have_graphs;
@@ -635,7 +636,7 @@ int capture(lbm_ec_batch* B, int steps, hipGraphExec_t* out) {
   hipError_t le = hipSuccess;
   for (int k = 0; k < steps && le == hipSuccess; ++k)
     le = ec::launch_batch_step<T, C>(B->d_desc, B->d_off, B->totals, (int)B->order.size(), B->lds, B->collide_lds,
-                                     B->tu, B->s);
+                                     B->fft8, B->tu, B->s);
   hipError_t ee = hipStreamEndCapture(B->s, &g);
   if (le != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture launch: ") + hipGetErrorString(le));
   if (ee != hipSuccess) return fail(LBM_EC_EHIP, std::string("batch capture: ") + hipGetErrorString(ee));
@@ -676,6 +677,7 @@ int rebuild(lbm_ec_batch* B) {
   std::vector<int> off((size_t)ec::BK_COUNT * (ns + 1), 0);
   B->lds = 0;
   B->collide_lds = 0;
+  B->fft8 = true;
   for (int k = 0; k < ec::BK_COUNT; ++k) B->totals[k] = 0;
   for (int q = 0; q < ns; ++q) {
     Slot& sl = B->slots[B->order[q]];
@@ -696,6 +698,7 @@ int rebuild(lbm_ec_batch* B) {
     const size_t clds = sl.inst.fp32 ? ec::collide_lds_bytes<float>(sl.inst.p.nx)
                                      : ec::collide_lds_bytes<double>(sl.inst.p.nx);
     B->collide_lds = std::max(B->collide_lds, clds);
+    B->fft8 = B->fft8 && ec::fft_in_place(sl.inst.plan, B->tu.fft_threads, 8);
     for (int k = 0; k < ec::BK_COUNT; ++k) {
       off[(size_t)k * (ns + 1) + q] = B->totals[k];
       B->totals[k] += ec::batch_blocks(d.c, k, B->tu);

@@ -168,9 +168,11 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu);
 // Enqueues one batched step (all kernels, then the device-side advance) for
 // ns slots.  d_off holds BK_COUNT rows of ns + 1 offsets; totals[k] is the
 // block count of launch k; lds the dynamic LDS of the transforms.
+// fft8: every slot's transform fits eight elements per thread (the lighter
+// kernel build).
 template <typename T, typename C>
 hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
-                             size_t collide_lds, const Tuning& tu, hipStream_t s);
+                             size_t collide_lds, bool fft8, const Tuning& tu, hipStream_t s);
 
 // Kernel launchers (ec_kernels.hip).  All enqueue on `s` and return the
 // launch status.

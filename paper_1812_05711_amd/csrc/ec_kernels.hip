@@ -171,7 +171,7 @@ __device__ __forceinline__ void generic_pass(const C2<T>* __restrict__ src, C2<T
 // same size).  Returns the buffer that holds the result.  Unnormalised:
 // forward uses exp(-2 pi i m x / N), inverse exp(+2 pi i m x / N).
 template <typename T, bool INV>
-__device__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftPlan& pl, const C2<T>* __restrict__ tw) {
+__device__ __forceinline__ C2<T>* fft_lds(C2<T>* a, C2<T>* b, const FftPlan& pl, const C2<T>* __restrict__ tw) {
   const int N = pl.n;
   int Ns = 1, off = 0;
   const C2<T>* twp = tw + N;  // pass-major twiddles follow the full table
@@ -240,7 +240,7 @@ __device__ __forceinline__ void stockham_pass_ip(C2<T>* __restrict__ buf, int N,
 // The same transform as fft_lds, in place in buffer a (requires
 // fft_in_place(pl, blockDim.x, F)).
 template <typename T, bool INV, int F>
-__device__ C2<T>* fft_lds_ip(C2<T>* a, const FftPlan& pl, const C2<T>* __restrict__ tw) {
+__device__ __forceinline__ C2<T>* fft_lds_ip(C2<T>* a, const FftPlan& pl, const C2<T>* __restrict__ tw) {
   const int N = pl.n;
   int Ns = 1;
   const C2<T>* twp = tw + N;
@@ -1471,13 +1471,13 @@ __device__ __forceinline__ bool slot_emits(const SlotDesc& d) {
   return k == d.steps_target || (d.emit_every > 0 && k % d.emit_every == 0);
 }
 
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(512) kb_forward(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
   const ChargeSrc<T> q{(const T*)d.b.rq, (const T*)d.b.eu, (const T*)d.b.ed, nullptr, nullptr};
-  forward_body<T, 0, kFftPerThread>(d.c, q, d.plan, (const C2<T>*)d.b.tw, (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny,
+  forward_body<T, 0, F>(d.c, q, d.plan, (const C2<T>*)d.b.tw, (C2<T>*)d.b.spec, d.b.rowsd + ROWD_DCSUM * d.c.ny,
                      blockIdx.x - off[s]);
 }
 
@@ -1514,12 +1514,12 @@ __global__ void __launch_bounds__(256) kb_tri_reduced(const SlotDesc* __restrict
   }
 }
 
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(512) kb_inverse(const SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
-  inverse_body<T, kFftPerThread>(d.c, (const C2<T>*)d.b.spec, (const T*)d.b.tt, (const C2<T>*)d.b.iface, d.plan,
+  inverse_body<T, F>(d.c, (const C2<T>*)d.b.spec, (const T*)d.b.tt, (const C2<T>*)d.b.iface, d.plan,
                   (const C2<T>*)d.b.tw, (T*)d.b.phi, blockIdx.x - off[s]);
 }
 
@@ -1540,54 +1540,52 @@ __global__ void __launch_bounds__(1024) kb_collide(const SlotDesc* __restrict__ 
                                     (T*)d.b.g[dst], (const T*)d.b.phi, (const T*)d.b.rows, d.b.rowsd, d.b.mom,
                                     (T*)d.b.rq, (T*)d.b.eu, (T*)d.b.ed, b);
 }
-// Diagnostics of the slots that emitted moments this step (one block each):
-// rms u_y, max |u| and the total charge, into the slot's history.
-__global__ void __launch_bounds__(256) kb_stats(SlotDesc* __restrict__ D, const int* __restrict__ off, int ns) {
-  __shared__ double red[32];
-  __shared__ double mx[256];
+// End of a batched step, one block per slot: the diagnostics of a slot that
+// emitted moments this step (rms u_y, max |u| and the total charge, into its
+// history), then the device-side advance of every active slot (flip the
+// buffers, count the step, retire the slot at its target), so a captured
+// multi-step graph needs no host updates.
+__global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D, const int* __restrict__ off,
+                                                        int ns) {
+  __shared__ double red[16];
   const int s = find_slot(off, ns, blockIdx.x);
-  const SlotDesc& d = D[s];
-  if (!d.active || !slot_emits(d) || d.hist == nullptr) return;
-  const long long k = d.steps_done + 1;
-  const int row = (d.emit_every > 0 && k % d.emit_every == 0) ? (int)(k / d.emit_every) - 1 : d.hist_cap - 1;
-  if (row < 0 || row >= d.hist_cap) return;
-  const size_t n = (size_t)d.c.ny * d.c.nx;
-  double suy = 0, srho_c = 0, mu = 0;
-  for (size_t q = threadIdx.x; q < n; q += blockDim.x) {
-    const int j = (int)(q / d.c.nx);
-    const double ux = d.b.mom[n + q], uy = d.b.mom[2 * n + q];
-    suy += uy * uy;
-    mu = fmax(mu, sqrt(ux * ux + uy * uy));
-    srho_c += d.b.rowsd[ROWD_R * d.c.ny + j] + d.b.mom[3 * n + q];
-  }
-  suy = block_sum(suy, red);
-  __syncthreads();
-  srho_c = block_sum(srho_c, red);
-  mx[threadIdx.x] = mu;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double* h = d.hist + 4 * (size_t)row;
-    h[0] = (double)k;
-    h[1] = sqrt(suy / (double)n);
-    h[2] = mx[0];
-    h[3] = srho_c;
-  }
-}
-
-// Device-side end of a batched step: flip the buffers of the active slots,
-// count the step, retire slots that reached their target.
-__global__ void kb_advance(SlotDesc* __restrict__ D, int ns) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ns) return;
   SlotDesc& d = D[s];
   if (!d.active) return;
-  d.cur = 1 - d.cur;
-  d.steps_done += 1;
-  if (d.steps_done >= d.steps_target) d.active = 0;
+  const long long k = d.steps_done + 1;  // the step just taken
+  if (slot_emits(d) && d.hist != nullptr) {
+    const int row = (d.emit_every > 0 && k % d.emit_every == 0) ? (int)(k / d.emit_every) - 1 : d.hist_cap - 1;
+    if (row >= 0 && row < d.hist_cap) {
+      const int nx = d.c.nx, ny = d.c.ny;
+      const size_t n = (size_t)ny * nx;
+      double suy = 0, srho_c = 0, mu = 0;
+      for (int j = 0; j < ny; ++j) {
+        const double r = d.b.rowsd[ROWD_R * ny + j];
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+          const size_t q = (size_t)j * nx + x;
+          const double ux = d.b.mom[n + q], uy = d.b.mom[2 * n + q];
+          suy += uy * uy;
+          mu = fmax(mu, sqrt(ux * ux + uy * uy));
+          srho_c += r + d.b.mom[3 * n + q];
+        }
+      }
+      suy = block_sum(suy, red);
+      srho_c = block_sum(srho_c, red);
+      mu = block_max(mu, red);
+      if (threadIdx.x == 0) {
+        double* h = d.hist + 4 * (size_t)row;
+        h[0] = (double)k;
+        h[1] = sqrt(suy / (double)n);
+        h[2] = mu;
+        h[3] = srho_c;
+      }
+    }
+  }
+  __syncthreads();  // every thread has read the step state
+  if (threadIdx.x == 0) {
+    d.cur = 1 - d.cur;
+    d.steps_done = k;
+    if (k >= d.steps_target) d.active = 0;
+  }
 }
 
 int batch_blocks(const Consts& c, int k, const Tuning& tu) {
@@ -1607,11 +1605,16 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu) {
 
 template <typename T, typename C>
 hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int* totals, int ns, size_t lds,
-                             size_t collide_lds, const Tuning& tu, hipStream_t s) {
+                             size_t collide_lds, bool fft8, const Tuning& tu, hipStream_t s) {
   const int row = ns + 1;
   SlotDesc* D = const_cast<SlotDesc*>(d_desc);
   if (totals[BK_FORWARD])
-    hipLaunchKernelGGL(kb_forward<T>, dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s, d_desc, d_off + BK_FORWARD * row, ns);
+    if (fft8)
+      hipLaunchKernelGGL((kb_forward<T, 8>), dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s, d_desc,
+                         d_off + BK_FORWARD * row, ns);
+    else
+      hipLaunchKernelGGL((kb_forward<T, kFftPerThread>), dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s,
+                         d_desc, d_off + BK_FORWARD * row, ns);
   if (totals[BK_TRI_LOCAL])
     hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(256), 0, s, d_desc,
                        d_off + BK_TRI_LOCAL * row, ns);
@@ -1619,21 +1622,25 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
     hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(256), 0, s, d_desc,
                        d_off + BK_TRI_REDUCED * row, ns);
   if (totals[BK_INVERSE])
-    hipLaunchKernelGGL(kb_inverse<T>, dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s, d_desc, d_off + BK_INVERSE * row, ns);
+    if (fft8)
+      hipLaunchKernelGGL((kb_inverse<T, 8>), dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s, d_desc,
+                         d_off + BK_INVERSE * row, ns);
+    else
+      hipLaunchKernelGGL((kb_inverse<T, kFftPerThread>), dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s,
+                         d_desc, d_off + BK_INVERSE * row, ns);
   if (totals[BK_COLLIDE])
     hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(tu.cbx * tu.cby), collide_lds, s, d_desc,
                        d_off + BK_COLLIDE * row, ns);
   if (totals[BK_STATS])
-    hipLaunchKernelGGL(kb_stats, dim3(totals[BK_STATS]), dim3(256), 0, s, D, d_off + BK_STATS * row, ns);
-  hipLaunchKernelGGL(kb_advance, dim3((ns + 63) / 64), dim3(64), 0, s, D, ns);
+    hipLaunchKernelGGL(kb_stats_advance, dim3(totals[BK_STATS]), dim3(256), 0, s, D, d_off + BK_STATS * row, ns);
   return hipGetLastError();
 }
 
-template hipError_t launch_batch_step<double, double>(const SlotDesc*, const int*, const int*, int, size_t, size_t,
+template hipError_t launch_batch_step<double, double>(const SlotDesc*, const int*, const int*, int, size_t, size_t, bool,
                                                      const Tuning&, hipStream_t);
-template hipError_t launch_batch_step<float, float>(const SlotDesc*, const int*, const int*, int, size_t, size_t,
+template hipError_t launch_batch_step<float, float>(const SlotDesc*, const int*, const int*, int, size_t, size_t, bool,
                                                    const Tuning&, hipStream_t);
-template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*, const int*, int, size_t, size_t,
+template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*, const int*, int, size_t, size_t, bool,
                                                     const Tuning&, hipStream_t);
 
 // ------------------------------------------------------------- launchers
