@@ -142,13 +142,17 @@ def sweep_section(steps, plain_steps):
 def serve_section(n, warmup, budget_gb):
     from paper_1812_05711_amd.serve import BatchBackend, make_requests, serve
 
+    from paper_1812_05711_amd import autotune
+
     reqs = make_requests(n, rate=50.0, steps=5000)
-    log(f"serve: {n} requests at 50/s, budget {budget_gb} GB")
-    be = BatchBackend(int(budget_gb * (1 << 30)), max_slots=512)
+    # launch shapes tuned on a sample of the stream's mix (before the clock starts)
+    tuning = autotune.tune_batch([r["params"] for r in reqs[:48]])
+    log(f"serve: {n} requests at 50/s, budget {budget_gb} GB, launch shapes {tuning}")
+    be = BatchBackend(int(budget_gb * (1 << 30)), max_slots=512, tuning=tuning)
     records, summary = serve(reqs, be, chunk=100, warmup=warmup, max_wall=600.0)
     be.close()
     summary.update({"rate_per_s": 50.0, "steps_per_request": 5000, "warmup_requests": warmup,
-                    "budget_bytes": int(budget_gb * (1 << 30)), "chunk_steps": 100})
+                    "budget_bytes": int(budget_gb * (1 << 30)), "chunk_steps": 100, "tuning": list(tuning)})
     log(f"serve: p50 {summary['p50_s']:.3f} s, p99 {summary['p99_s']:.3f} s, {summary['runs_per_s']:.1f} runs/s")
     return summary
 

@@ -304,6 +304,13 @@ __device__ double block_sum(double v, double* red) {
 __device__ __forceinline__ int wrap_m(int x, int nx) { return x == 0 ? nx - 1 : x - 1; }
 __device__ __forceinline__ int wrap_p(int x, int nx) { return x == nx - 1 ? 0 : x + 1; }
 
+// Streaming load: each population is read once per step, so it should not
+// displace the smaller fields (potential, spectrum, charge sums) from L2.
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // The pulls below choose their source addresses with selects instead of
 // branches, so that all nine loads of a node are issued before the first one
 // is used (branches around loads serialise them on memory latency).  Offsets
@@ -328,11 +335,11 @@ __device__ __forceinline__ void pull_g(const Consts& c, const T* __restrict__ G,
   // above the node: streamed from row j+1, or the same-row neighbours at the
   // collector (zero normal gradient)
   const unsigned o4 = ra + x, o7 = ra + xp, o8 = ra + xm;
-  const T a0 = G[row + x];
-  const T a1 = G[plane + row + xm];
-  const T a3 = G[3 * plane + row + xp];
-  const T a2 = p2[o2], a5 = p5[o5], a6 = p6[o6];
-  const T a4 = G[4 * plane + o4], a7 = G[7 * plane + o7], a8 = G[8 * plane + o8];
+  const T a0 = ldnt(&G[row + x]);
+  const T a1 = ldnt(&G[plane + row + xm]);
+  const T a3 = ldnt(&G[3 * plane + row + xp]);
+  const T a2 = ldnt(&p2[o2]), a5 = ldnt(&p5[o5]), a6 = ldnt(&p6[o6]);
+  const T a4 = ldnt(&G[4 * plane + o4]), a7 = ldnt(&G[7 * plane + o7]), a8 = ldnt(&G[8 * plane + o8]);
   const T ua = rows[ROW_DG_UP_AXIS * c.ny + j], ud = rows[ROW_DG_UP_DIAG * c.ny + j];
   const T da = rows[ROW_DG_DN_AXIS * c.ny + j], dd = rows[ROW_DG_DN_DIAG * c.ny + j];
   g[0] = a0;
@@ -362,15 +369,15 @@ __device__ __forceinline__ void pull_f(const Consts& c, const T* __restrict__ F,
   const T* p4 = F + (hi ? 4 : 2) * plane;
   const T* p7 = F + (hi ? 7 : 5) * plane;
   const T* p8 = F + (hi ? 8 : 6) * plane;
-  f[0] = F[row + x];
-  f[1] = F[plane + row + xm];
-  f[3] = F[3 * plane + row + xp];
-  f[2] = p2[rb + x];
-  f[5] = p5[rb + (lo ? xm : x)];
-  f[6] = p6[rb + (lo ? xp : x)];
-  f[4] = p4[ra + x];
-  f[7] = p7[ra + (hi ? xp : x)];
-  f[8] = p8[ra + (hi ? xm : x)];
+  f[0] = ldnt(&F[row + x]);
+  f[1] = ldnt(&F[plane + row + xm]);
+  f[3] = ldnt(&F[3 * plane + row + xp]);
+  f[2] = ldnt(&p2[rb + x]);
+  f[5] = ldnt(&p5[rb + (lo ? xm : x)]);
+  f[6] = ldnt(&p6[rb + (lo ? xp : x)]);
+  f[4] = ldnt(&p4[ra + x]);
+  f[7] = ldnt(&p7[ra + (hi ? xp : x)]);
+  f[8] = ldnt(&p8[ra + (hi ? xm : x)]);
 }
 
 template <typename T>
@@ -1153,9 +1160,10 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
   const size_t idx = row + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    Fout[i * plane + idx] = (T)fo[i];
+    // streaming stores: the populations are read again only next step
+    __builtin_nontemporal_store((T)fo[i], &Fout[i * plane + idx]);
     gout[i] = (T)go[i];
-    Gout[i * plane + idx] = gout[i];
+    __builtin_nontemporal_store(gout[i], &Gout[i * plane + idx]);
   }
 }
 
