@@ -22,6 +22,9 @@ FLAGS = [
     "-fPIC",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, so a kernel
+    # body gives the same rounding in every kernel it is inlined into
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -1056,21 +1056,28 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
                                              const T* __restrict__ phi, const T* __restrict__ rows,
                                              const double* __restrict__ rowsd, double* __restrict__ mom, int x, int j,
                                              T gout[9]) {
+  // every load of the node first (populations, then the potential around
+  // it), so that they are in flight together; the scheduling barrier keeps
+  // the compiler from interleaving the first uses with them
+  const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+  const size_t row = (size_t)j * c.P;
+  const bool lo = j > 0, hi = j < c.ny - 1;
+  T ft[9], gt[9];
+  if (PULL) {
+    pull_f<T>(c, Fin, x, j, ft);
+    pull_g<T>(c, Gin, rows, x, j, gt);
+  } else {
+    local_pop<T>(c, Fin, x, j, ft);
+    local_pop<T>(c, Gin, x, j, gt);
+  }
+  const T pcT = phi[row + x], pxpT = phi[row + xp], pxmT = phi[row + xm];
+  const T pynT = phi[(hi ? row + c.P : row) + x], pysT = phi[(lo ? row - c.P : row) + x];
+  __builtin_amdgcn_sched_barrier(0);
   C f[9], g[9];
-  {
-    T ft[9], gt[9];
-    if (PULL) {
-      pull_f<T>(c, Fin, x, j, ft);
-      pull_g<T>(c, Gin, rows, x, j, gt);
-    } else {
-      local_pop<T>(c, Fin, x, j, ft);
-      local_pop<T>(c, Gin, x, j, gt);
-    }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      f[i] = (C)ft[i];
-      g[i] = (C)gt[i];
-    }
+  for (int i = 0; i < 9; ++i) {
+    f[i] = (C)ft[i];
+    g[i] = (C)gt[i];
   }
   // moments
   const C drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
@@ -1079,15 +1086,13 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
   const C jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
   const C drc = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
   const C rc = (C)rows[ROW_R * c.ny + j] + drc;
-  // electric field
-  const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
-  const size_t row = (size_t)j * c.P;
-  const C pc = (C)phi[row + x];
-  const C pxp = (C)phi[row + xp], pxm = (C)phi[row + xm];
-  const C pyp = j < c.ny - 1 ? (C)phi[row + c.P + x] : -pc;
-  const C pym = j > 0 ? (C)phi[row - c.P + x] : -pc;
-  const C ex = -(pxp - pxm) / C(2);
-  const C eyf = -(pyp - pym) / C(2);  // transverse-mode part of E_y
+  // electric field: central differences; the ghost rows of the fluctuation
+  // potential are its odd reflections (-phi) at both walls
+  const C pc = (C)pcT, pxp = (C)pxpT, pxm = (C)pxmT;
+  const C pyp = hi ? (C)pynT : -pc;
+  const C pym = lo ? (C)pysT : -pc;
+  const C ex = C(-0.5) * (pxp - pxm);
+  const C eyf = C(-0.5) * (pyp - pym);  // transverse-mode part of E_y
   const C ey = C(rowsd[ROWD_EYM * c.ny + j]) + eyf;
   const C fx = rc * ex + C(c.bx);
   // y force less the reference force s/3, without forming the large terms:
@@ -1095,8 +1100,9 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
   const C dfy = C(rowsd[ROWD_DFY * c.ny + j]) + (C)rows[ROW_R * c.ny + j] * eyf + drc * ey;
   const C fy = C(c.s_ref / 3.0) + dfy;
   // Eq. 7 on the deviations: sum_i c_i f_ref,i = -(s/6) y-hat cancels s/3 / 2
-  const C ux = (jx + C(0.5) * fx) / rho;
-  const C uy = (jy + C(0.5) * dfy) / rho;
+  const C irho = C(1) / rho;
+  const C ux = (jx + C(0.5) * fx) * irho;
+  const C uy = (jy + C(0.5) * dfy) * irho;
   const C vx = ux + C(c.K) * ex;
   const C vy = uy + C(c.K) * ey;
   if (mom != nullptr) {
@@ -1106,26 +1112,34 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
     mom[2 * n + k] = (double)uy;
     mom[3 * n + k] = (double)drc;
   }
+  // TRT on the symmetric / antisymmetric parts of each pair (i, opp):
+  //   f^eq_i - w_i rho_ref = w_i drho + w_i rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+  //     -> symmetric w drho + w rho (4.5 (c.u)^2 - 1.5 u.u), antisymmetric w rho 3 c.u
+  //   F_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F with its part 3 w_i c_iy s/3
+  //     carried by the reference (3 c.(F - s/3 y-hat) in place of 3 c.F)
+  //     -> symmetric w (9 (c.u)(c.F) - 3 u.F), antisymmetric 3 w c.(F - s/3 y-hat)
+  //   charge: g^eq_i - R_i = w_i drc + w_i rc (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)
+  //   post-collision: f_i - [w+ (f+ - e+) - (1 - w+/2) S+] -/+ [w- (f- - e-) - (1 - w-/2) S-]
   const C w0 = C(4.0 / 9.0), wa = C(1.0 / 9.0), wd = C(1.0 / 36.0);
-  const C uu = ux * ux + uy * uy;
-  const C vv = vx * vx + vy * vy;
-  // f^eq_i - w_i rho_ref = w_i drho + w_i rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
-  // F_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F; its part 3 w_i c_iy s/3 is
-  // carried by the reference, so the source on the deviations uses
-  // 3 c.(F - s/3 y-hat) in place of 3 c.F
-  // charge: g^eq_i - R_i = w_i drc + w_i rc (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)
   const C wp = C(c.wp), wm = C(c.wm), wgp = C(c.wgp), wgm = C(c.wgm);
   const C sp = C(1) - C(0.5) * wp, sm = C(1) - C(0.5) * wm;
+  const C uu15 = C(1.5) * (ux * ux + uy * uy);
+  const C vv15 = C(1.5) * (vx * vx + vy * vy);
   const C uF = ux * fx + uy * fy;
-  C fo[9], go[9];
+  const size_t plane = (size_t)c.ny * c.P;
+  const size_t idx = row + x;
+  // streaming stores: the populations are read again only next step
+  auto put = [&](int i, C fv, C gv) {
+    __builtin_nontemporal_store((T)fv, &Fout[i * plane + idx]);
+    gout[i] = (T)gv;
+    __builtin_nontemporal_store(gout[i], &Gout[i * plane + idx]);
+  };
   {  // rest direction
-    const C feq0 = w0 * drho + w0 * rho * (-C(1.5) * uu);
-    const C F0 = w0 * (-C(3) * uF);
-    fo[0] = f[0] - wp * (f[0] - feq0) + sp * F0;
-    const C geq0 = w0 * drc + w0 * rc * (-C(1.5) * vv);
-    go[0] = g[0] - wgp * (g[0] - geq0);
+    const C feq0 = w0 * drho - (w0 * rho) * uu15;
+    const C F0 = -(C(3) * w0) * uF;
+    const C geq0 = w0 * drc - (w0 * rc) * vv15;
+    put(0, f[0] - wp * (f[0] - feq0) + sp * F0, g[0] - wgp * (g[0] - geq0));
   }
-  // pairs (i, opp): (1,3), (2,4), (5,7), (6,8)
   const int pi[4] = {1, 2, 5, 6}, po[4] = {3, 4, 7, 8};
   const C cxs[4] = {C(1), C(0), C(1), C(-1)}, cys[4] = {C(0), C(1), C(1), C(1)};
 #pragma unroll
@@ -1137,33 +1151,21 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
     const C cv = cx * vx + cy * vy;
     const C cF = cx * fx + cy * fy;
     const C cdF = cx * fx + cy * dfy;
-    // equilibria at i (c) and at opp (-c)
-    const C fe_i = w * drho + w * rho * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu);
-    const C fe_o = w * drho + w * rho * (-C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu);
-    const C Fs_i = w * (C(3) * (cdF - uF) + C(9) * cu * cF);
-    const C Fs_o = w * (C(3) * (-cdF - uF) + C(9) * cu * cF);
-    const C ge_i = w * drc + w * rc * (C(3) * cv + C(4.5) * cv * cv - C(1.5) * vv);
-    const C ge_o = w * drc + w * rc * (-C(3) * cv + C(4.5) * cv * cv - C(1.5) * vv);
+    const C wr = w * rho, wc = w * rc;
+    const C ep = w * drho + wr * (C(4.5) * cu * cu - uu15);
+    const C em = wr * (C(3) * cu);
+    const C Sp = w * (C(9) * cu * cF - C(3) * uF);
+    const C Sm = (C(3) * w) * cdF;
     const C fp = C(0.5) * (f[i] + f[o]), fm = C(0.5) * (f[i] - f[o]);
-    const C ep = C(0.5) * (fe_i + fe_o), em = C(0.5) * (fe_i - fe_o);
-    const C Sp = C(0.5) * (Fs_i + Fs_o), Sm = C(0.5) * (Fs_i - Fs_o);
-    const C relp = wp * (fp - ep), relm = wm * (fm - em);
-    fo[i] = f[i] - relp - relm + sp * Sp + sm * Sm;
-    fo[o] = f[o] - relp + relm + sp * Sp - sm * Sm;
+    const C A = wp * (fp - ep) - sp * Sp;
+    const C B = wm * (fm - em) - sm * Sm;
+    const C hp = w * drc + wc * (C(4.5) * cv * cv - vv15);
+    const C hm = wc * (C(3) * cv);
     const C gp = C(0.5) * (g[i] + g[o]), gm = C(0.5) * (g[i] - g[o]);
-    const C hp = C(0.5) * (ge_i + ge_o), hm = C(0.5) * (ge_i - ge_o);
-    const C grp = wgp * (gp - hp), grm = wgm * (gm - hm);
-    go[i] = g[i] - grp - grm;
-    go[o] = g[o] - grp + grm;
-  }
-  const size_t plane = (size_t)c.ny * c.P;
-  const size_t idx = row + x;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    // streaming stores: the populations are read again only next step
-    __builtin_nontemporal_store((T)fo[i], &Fout[i * plane + idx]);
-    gout[i] = (T)go[i];
-    __builtin_nontemporal_store(gout[i], &Gout[i * plane + idx]);
+    const C Ag = wgp * (gp - hp);
+    const C Bg = wgm * (gm - hm);
+    put(i, (f[i] - A) - B, (g[i] - Ag) - Bg);
+    put(o, (f[o] - A) + B, (g[o] - Ag) + Bg);
   }
 }
 
