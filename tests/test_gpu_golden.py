@@ -1,7 +1,8 @@
 """Parity at the full 1024 x 840 single-instance configuration (T = 300,
-C = 10, M = 10, Fe = 4000, noise 1e-3), against oracle fields stored by
-tests/golden/make_oracle_golden.py (oracle only) on a stride-8 subsample,
-normalised by the oracle's full-grid max |X|.
+C = 10, M = 10, Fe = 4000, noise 1e-3, 10000 steps) and on a 100-step
+prefix of the 4096 x 4096 bandwidth configuration (T = 500, noise 1e-4),
+against oracle fields stored by tests/golden/make_oracle_golden.py (oracle
+only) on a strided subsample, normalised by the oracle's full-grid max |X|.
 
 FP64 storage must match to 1e-11 and FP32-deviation storage with FP64
 collision arithmetic to 1e-5 on every field.  FP32-deviation storage with
@@ -20,12 +21,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "oracle_cfg1.npz")
 KW = dict(nx=1024, ny=840, T=300.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25,
           Lambda_g=1e-6, noise_amp=1e-3, seed=181205711)
+GOLDEN2 = os.path.join(HERE, "golden", "oracle_cfg2_prefix.npz")
+KW2 = dict(nx=4096, ny=4096, T=500.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25,
+           Lambda_g=1e-6, noise_amp=1e-4, seed=181205711)
 
 
-def _golden():
-    if not os.path.exists(GOLDEN):
-        pytest.skip("oracle golden for 1024 x 840 not generated yet (tests/golden/make_oracle_golden.py cfg1)")
-    return np.load(GOLDEN)
+def _golden(path=GOLDEN, what="1024 x 840", case="cfg1"):
+    if not os.path.exists(path):
+        pytest.skip(f"oracle golden for {what} not generated yet (tests/golden/make_oracle_golden.py {case})")
+    return np.load(path)
 
 
 def _errors(gold, f, step):
@@ -39,12 +43,12 @@ def _errors(gold, f, step):
     return e
 
 
-def _run(precision, snaps):
+def _run(precision, snaps, kw=KW):
     import torch
 
     from paper_1812_05711_amd.lbm_ec import Simulation
 
-    sim = Simulation(device="cuda:0", precision=precision, **KW)
+    sim = Simulation(device="cuda:0", precision=precision, **kw)
     out = {}
     for s in snaps:
         sim.step(s - sim.steps_done())
@@ -66,3 +70,16 @@ def test_cfg1_against_oracle(precision, tol, utol):
         for k in ("rho", "rho_c", "phi"):
             assert e[k] <= tol, (precision, s, k, e)
         assert e["u"] <= utol, (precision, s, e)
+
+
+@pytest.mark.parametrize("precision", ["fp32_f64math", "fp32"])
+def test_cfg2_prefix_against_oracle(precision):
+    """4096 x 4096 (FP32 storage; FP64 storage is limited to nx <= 2048),
+    100 steps: every field within 1e-5 (the FP32-arithmetic velocity drift of
+    the long runs has not built up after 100 steps)."""
+    gold = _golden(GOLDEN2, "4096 x 4096", "cfg2_prefix")
+    res = _run(precision, [100], KW2)
+    e = _errors(gold, res[100], 100)
+    print(precision, 100, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k in ("rho", "rho_c", "phi", "u"):
+        assert e[k] <= 1e-5, (precision, k, e)
