@@ -185,9 +185,8 @@ hipError_t launch_init_populations(const Consts& c, const Bufs& b, int dst, hipS
 template <typename T>
 hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int mode, int src,
                           const Tuning& tu, hipStream_t s);
-// the x-mean mode (beside the chunk-local solves of the m >= 1 y systems),
-// then the interface system (the chunk corrections are applied by
-// launch_inverse)
+// chunk-local solves of the m >= 1 y systems, then the interface system
+// (the chunk corrections, and the x-mean mode, are done by launch_inverse)
 template <typename T>
 hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s);
 template <typename T>

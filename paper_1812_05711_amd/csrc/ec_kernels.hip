@@ -713,17 +713,10 @@ __device__ __forceinline__ void tri_local_body(const Consts& c, const T* __restr
   ends[(2 * (size_t)k + 1) * MP + m] = last;
 }
 
-// Block 0 solves the x-mean mode (independent of the m >= 1 solves, so it
-// runs beside them); blocks 1.. are the chunk-local solves.
 template <typename T>
 __global__ void __launch_bounds__(256) k_tri_local(Consts c, const T* __restrict__ tt, C2<T>* __restrict__ spec,
-                                                   C2<T>* __restrict__ ends, double* __restrict__ rowsd,
-                                                   double* __restrict__ dmean) {
-  if (blockIdx.x == 0) {
-    mean_mode_body(c, rowsd, dmean);
-    return;
-  }
-  const int b = blockIdx.x - 1;
+                                                   C2<T>* __restrict__ ends) {
+  const int b = blockIdx.x;
   const int nbx = (c.M - 1 + blockDim.x - 1) / blockDim.x;
   tri_local_body<T>(c, tt, spec, ends, b % nbx, b / nbx);
 }
@@ -1033,11 +1026,19 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
   }
 }
 
+// Block 0 solves the x-mean mode (needed only by the collision, and
+// independent of the m >= 1 modes, so it runs beside the transforms);
+// blocks 1.. are the row pairs.
 template <typename T, int F>
 __global__ void __launch_bounds__(512) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
                                                  const C2<T>* __restrict__ iface, FftPlan pl,
-                                                 const C2<T>* __restrict__ tw, T* __restrict__ phi) {
-  inverse_body<T, F>(c, spec, tt, iface, pl, tw, phi, blockIdx.x);
+                                                 const C2<T>* __restrict__ tw, T* __restrict__ phi,
+                                                 double* __restrict__ rowsd, double* __restrict__ dmean) {
+  if (blockIdx.x == 0) {
+    mean_mode_body(c, rowsd, dmean);
+    return;
+  }
+  inverse_body<T, F>(c, spec, tt, iface, pl, tw, phi, blockIdx.x - 1);
 }
 
 // ------------------------------------------- fused collide (and stream)
@@ -1498,12 +1499,8 @@ __global__ void __launch_bounds__(256) kb_tri_local(const SlotDesc* __restrict__
   const SlotDesc& d = D[s];
   if (!d.active) return;
   const int lb = blockIdx.x - off[s];
-  if (lb == 0) {
-    mean_mode_body(d.c, d.b.rowsd, d.b.dmean);
-    return;
-  }
   const int nbx = (d.c.M - 1 + blockDim.x - 1) / blockDim.x;
-  tri_local_body<T>(d.c, (const T*)d.b.tt, (C2<T>*)d.b.spec, (C2<T>*)d.b.ends, (lb - 1) % nbx, (lb - 1) / nbx);
+  tri_local_body<T>(d.c, (const T*)d.b.tt, (C2<T>*)d.b.spec, (C2<T>*)d.b.ends, lb % nbx, lb / nbx);
 }
 
 // 256 threads per block: four wavenumbers per block on the scan path, 256 on
@@ -1529,8 +1526,13 @@ __global__ void __launch_bounds__(512) kb_inverse(const SlotDesc* __restrict__ D
   const int s = find_slot(off, ns, blockIdx.x);
   const SlotDesc& d = D[s];
   if (!d.active) return;
+  const int lb = blockIdx.x - off[s];
+  if (lb == 0) {
+    mean_mode_body(d.c, d.b.rowsd, d.b.dmean);
+    return;
+  }
   inverse_body<T, F>(d.c, (const C2<T>*)d.b.spec, (const T*)d.b.tt, (const C2<T>*)d.b.iface, d.plan,
-                  (const C2<T>*)d.b.tw, (T*)d.b.phi, blockIdx.x - off[s]);
+                     (const C2<T>*)d.b.tw, (T*)d.b.phi, lb - 1);
 }
 
 template <typename T, typename C>
@@ -1601,9 +1603,9 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
 int batch_blocks(const Consts& c, int k, const Tuning& tu) {
   const int nm = c.M - 1;
   switch (k) {
-    case BK_FORWARD:
-    case BK_INVERSE: return (c.ny + 1) / 2;
-    case BK_TRI_LOCAL: return 1 + (nm > 0 ? ((nm + 255) / 256) * c.NC : 0);
+    case BK_FORWARD: return (c.ny + 1) / 2;
+    case BK_INVERSE: return 1 + (c.ny + 1) / 2;  // block 0: the x-mean mode
+    case BK_TRI_LOCAL: return nm > 0 ? ((nm + 255) / 256) * c.NC : 0;
     case BK_TRI_REDUCED:
       if (nm <= 0 || c.NC < 2) return 0;
       return c.NC - 1 <= kScanMax ? (nm + 3) / 4 : (nm + 255) / 256;
@@ -1698,11 +1700,11 @@ hipError_t launch_forward(const Consts& c, const Bufs& b, const FftPlan& pl, int
 template <typename T>
 hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
   const int nm = c.M - 1;
-  const int nloc = nm > 0 ? ((nm + 255) / 256) * c.NC : 0;
-  hipLaunchKernelGGL(k_tri_local<T>, dim3(1 + nloc), dim3(256), 0, s, c, (const T*)b.tt, (C2<T>*)b.spec,
-                     (C2<T>*)b.ends, b.rowsd, b.dmean);
+  if (nm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tri_local<T>, dim3(((nm + 255) / 256) * c.NC), dim3(256), 0, s, c, (const T*)b.tt,
+                     (C2<T>*)b.spec, (C2<T>*)b.ends);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || nm <= 0 || c.NC < 2) return e;
+  if (e != hipSuccess || c.NC < 2) return e;
   if (c.NC - 1 <= kScanMax)
     hipLaunchKernelGGL(k_tri_scan<T>, dim3((nm + 3) / 4), dim3(256), 0, s, c, (const T*)b.rf,
                        (const C2<T>*)b.ends, (C2<T>*)b.iface);
@@ -1714,14 +1716,14 @@ hipError_t launch_tridiag(const Consts& c, const Bufs& b, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, const Tuning& tu, hipStream_t s) {
-  dim3 blk(tu.fft_threads), grd((c.ny + 1) / 2);
+  dim3 blk(tu.fft_threads), grd(1 + (c.ny + 1) / 2);  // block 0: the x-mean mode
   const size_t lds = fft_lds_bytes<T>(pl, tu.fft_threads);
   if (fft_in_place(pl, tu.fft_threads, 8))
     hipLaunchKernelGGL((k_inverse<T, 8>), grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
-                       (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
+                       (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi, b.rowsd, b.dmean);
   else
     hipLaunchKernelGGL((k_inverse<T, kFftPerThread>), grd, blk, lds, s, c, (const C2<T>*)b.spec, (const T*)b.tt,
-                       (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi);
+                       (const C2<T>*)b.iface, pl, (const C2<T>*)b.tw, (T*)b.phi, b.rowsd, b.dmean);
   return hipGetLastError();
 }
 
