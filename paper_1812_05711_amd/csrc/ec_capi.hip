@@ -31,8 +31,8 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Largest x transform the LDS budget of one workgroup allows (two complex
-// buffers of n elements within 64 KiB).
+// Widest grid: a collide tile holds ten rows of nx values of the storage
+// type in LDS, at most 160 KiB per workgroup.
 int max_nx(int precision) { return precision == LBM_EC_FP64 ? 2048 : 4096; }
 
 // v rounded to `bits` significant bits, ties to even.
@@ -870,6 +870,7 @@ int lbm_ec_batch_fields(lbm_ec_batch_t* B, int32_t slot, double* rho, double* ux
 
 int lbm_ec_batch_history(lbm_ec_batch_t* B, int32_t slot, double* out, int32_t rows) {
   if (!B || !out || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
+  if (rows < 0) return fail(LBM_EC_EINVAL, "rows must be non-negative");
   const int r = std::min(rows, B->hist_rows);
   EC_HIP(hipMemcpyAsync(out, B->slots[slot].hist, sizeof(double) * 4 * r, hipMemcpyDeviceToHost, B->s));
   EC_HIP(hipStreamSynchronize(B->s));
@@ -981,47 +982,7 @@ int lbm_ec_create(const lbm_ec_params* p, void* d_ws, size_t ws_bytes, void* hip
     return fail(LBM_EC_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
   if (((uintptr_t)d_ws) % kAlign) return fail(LBM_EC_ENOMEM, "workspace must be 256-byte aligned");
   lbm_ec* h = new lbm_ec();
-  h->p = *p;
-  h->L = L;
-  h->s = (hipStream_t)hip_stream;
-  h->fp32 = p->precision != LBM_EC_FP64;
-  h->plan = make_plan(p->nx);
-  h->tu = default_tuning(p->nx);
-  unsigned char* ws = (unsigned char*)d_ws;
-  h->b.f[0] = ws + L.off_f[0];
-  h->b.f[1] = ws + L.off_f[1];
-  h->b.g[0] = ws + L.off_g[0];
-  h->b.g[1] = ws + L.off_g[1];
-  h->b.phi = ws + L.off_phi;
-  h->b.rq = ws + L.off_rq;
-  h->b.eu = ws + L.off_eu;
-  h->b.ed = ws + L.off_ed;
-  h->b.spec = ws + L.off_spec;
-  h->b.tt = ws + L.off_tt;
-  h->b.ends = ws + L.off_ends;
-  h->b.gh = ws + L.off_gh;
-  h->b.rf = ws + L.off_rf;
-  h->b.iface = ws + L.off_iface;
-  h->b.tw = ws + L.off_tw;
-  h->b.rows = ws + L.off_rows;
-  h->b.rowsd = (double*)(ws + L.off_rowsd);
-  h->b.dmean = (double*)(ws + L.off_dmean);
-  h->b.mom = (double*)(ws + L.off_mom);
-  h->b.stats = (double*)(ws + L.off_stats);
-  h->b.spart = (double*)(ws + L.off_spart);
-  rc = h->fp32 ? setup<float>(h, ws) : setup<double>(h, ws);
-  if (!rc) {
-    if (p->precision == LBM_EC_FP64)
-      rc = init_state<double, double>(h);
-    else if (p->precision == LBM_EC_FP32_DEV)
-      rc = init_state<float, float>(h);
-    else
-      rc = init_state<float, double>(h);
-  }
-  if (!rc) {
-    hipError_t e = hipStreamSynchronize(h->s);
-    if (e != hipSuccess) rc = fail(LBM_EC_EHIP, std::string("initial state: ") + hipGetErrorString(e));
-  }
+  rc = build_instance(h, p, (unsigned char*)d_ws, (hipStream_t)hip_stream);
   if (rc) {
     delete h;
     return rc;
