@@ -81,6 +81,13 @@ def test_fp32_storage_small(nx, ny, steps, precision):
     _check(dict(BASE, nx=nx, ny=ny, precision=precision), steps, TOL32)
 
 
+@pytest.mark.parametrize("precision,nx", [("fp64", 2048), ("fp32_f64math", 4096), ("fp32", 4096)])
+def test_widest_grid(precision, nx):
+    """The widest row each storage type allows (whole rows in one collide
+    tile's LDS; the longest x transform)."""
+    _check(dict(BASE, nx=nx, ny=12, precision=precision), 20, TOL64 if precision == "fp64" else TOL32)
+
+
 def test_fp32_f64math_full_122x100_2000_steps():
     _check(dict(BASE, nx=122, ny=100, precision="fp32_f64math"), 2000, TOL32)
 

@@ -1,6 +1,7 @@
 """Parity of the Poisson chain alone (x transforms, per-wavenumber y solves
 on both interface-solve paths, the x-mean mode) with the oracle's solve,
-through lbm_ec_poisson, on seeded charge fields.
+through lbm_ec_poisson, on seeded charge fields, up to the widest grids
+(nx = 2048 in FP64, 4096 in FP32 storage; a wider FP64 grid is refused).
 
 The y systems split into chunks of 32 rows; the cases give interface
 systems of 0 (one chunk), 1, 26, 127 and 512 interfaces (recursive
@@ -20,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 BASE = dict(T=200.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6, noise_amp=1e-3,
             seed=181205711)
-CASES = [(16, 20), (24, 40), (40, 840), (8, 4096), (6, 16416), (6, 16480)]
+CASES = [(16, 20), (24, 40), (40, 840), (8, 4096), (6, 16416), (6, 16480), (2048, 24), (4096, 24)]
 TOL = {"fp64": 1e-11, "fp32_f64math": 1e-6, "fp32": 1e-6}
 
 
@@ -38,6 +39,14 @@ def test_poisson_matches_oracle(nx, ny, precision):
     from paper_1812_05711_amd.lbm_ec import Simulation
 
     kw = dict(BASE, nx=nx, ny=ny)
+    if precision == "fp64" and nx > 2048:
+        # the widest FP64 grid is 2048 (ten LDS rows of the collide tiles)
+        from paper_1812_05711_amd.lbm_ec import EINVAL, LbmEcError
+
+        with pytest.raises(LbmEcError) as ei:
+            Simulation(device="cuda:0", precision=precision, **kw)
+        assert ei.value.code == EINVAL
+        return
     rho_nd = _charge(nx, ny, 7 + nx + ny)
     eps = lattice_constants(Params(**kw)).eps
     phi_o = solve(rho_nd * eps / float(ny) ** 2, eps)
