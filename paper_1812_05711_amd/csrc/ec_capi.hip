@@ -585,7 +585,7 @@ namespace {
 size_t batch_header_bytes(int max_slots, int hist_rows) {
   size_t o = align_up(sizeof(ec::SlotDesc) * (size_t)max_slots);
   o += align_up(sizeof(int) * (size_t)ec::BK_COUNT * (max_slots + 1));
-  o += align_up(sizeof(double) * 4 * (size_t)hist_rows * max_slots);
+  o += align_up(sizeof(double) * ec::kHistCols * (size_t)hist_rows * max_slots);
   return o;
 }
 
@@ -776,7 +776,7 @@ int lbm_ec_batch_create(int32_t max_slots, int32_t precision, int32_t emit_every
   o += align_up(sizeof(int) * (size_t)ec::BK_COUNT * (max_slots + 1));
   B->d_hist = (double*)(B->ws + o);
   B->hist_rows = hist_rows;
-  o += align_up(sizeof(double) * 4 * (size_t)hist_rows * max_slots);
+  o += align_up(sizeof(double) * ec::kHistCols * (size_t)hist_rows * max_slots);
   B->heap_off = o;
   B->free_list.push_back(Range{o, ws_bytes - o});
   B->dirty = true;
@@ -817,9 +817,9 @@ int lbm_ec_batch_admit(lbm_ec_batch_t* B, const lbm_ec_params* p, int64_t n_step
   sl.off = off;
   sl.bytes = L.total;
   sl.target = n_steps;
-  sl.hist = B->d_hist + 4 * (size_t)B->hist_rows * idx;
+  sl.hist = B->d_hist + ec::kHistCols * (size_t)B->hist_rows * idx;
   sl.hist_cap = B->hist_rows;
-  EC_HIP(hipMemsetAsync(sl.hist, 0, sizeof(double) * 4 * B->hist_rows, B->s));
+  EC_HIP(hipMemsetAsync(sl.hist, 0, sizeof(double) * ec::kHistCols * B->hist_rows, B->s));
   B->dirty = true;
   *slot = idx;
   return LBM_EC_OK;
@@ -872,7 +872,7 @@ int lbm_ec_batch_history(lbm_ec_batch_t* B, int32_t slot, double* out, int32_t r
   if (!B || !out || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
   if (rows < 0) return fail(LBM_EC_EINVAL, "rows must be non-negative");
   const int r = std::min(rows, B->hist_rows);
-  EC_HIP(hipMemcpyAsync(out, B->slots[slot].hist, sizeof(double) * 4 * r, hipMemcpyDeviceToHost, B->s));
+  EC_HIP(hipMemcpyAsync(out, B->slots[slot].hist, sizeof(double) * ec::kHistCols * r, hipMemcpyDeviceToHost, B->s));
   EC_HIP(hipStreamSynchronize(B->s));
   return LBM_EC_OK;
 }

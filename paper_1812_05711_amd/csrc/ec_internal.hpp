@@ -39,6 +39,10 @@ __host__ __device__ inline int tile_rows(int ny) { return ny >= 512 ? (ny / 256 
 // Bands of rows reduced by separate blocks in the diagnostics.
 constexpr int kStatsBands = 1024;
 
+// Doubles per row of a batch slot's diagnostics history: step, rms u_y,
+// max |u|, sum of rho_c, amplitude of the first x mode of u_y (lattice units).
+constexpr int kHistCols = 5;
+
 // Rows per chunk of the partitioned per-wavenumber solves.
 constexpr int kChunk = 32;
 // Chunk types: the whole column (one chunk), the first one (lower electrode
@@ -149,7 +153,7 @@ struct SlotDesc {
   int emit_every;      // moments and diagnostics every emit_every steps and at the end
   int hist_cap;        // rows of the diagnostics history
   long long steps_done, steps_target;
-  double* hist;        // [hist_cap][4]: step, rms u_y, max |u|, sum of rho_c (lattice units)
+  double* hist;        // [hist_cap][kHistCols], see kb_stats_advance
 };
 
 // Launch shapes that do not change results: threads per x-transform block

@@ -1569,26 +1569,38 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
     if (row >= 0 && row < d.hist_cap) {
       const int nx = d.c.nx, ny = d.c.ny;
       const size_t n = (size_t)ny * nx;
-      double suy = 0, srho_c = 0, mu = 0;
+      // a1: the largest over the rows of |sum_x u_y exp(-2 pi i x / nx)| / nx,
+      // the amplitude of the first x mode (the perturbation whose growth or
+      // decay marks the electroconvective threshold)
+      double suy = 0, srho_c = 0, mu = 0, a1 = 0;
       for (int j = 0; j < ny; ++j) {
         const double r = d.b.rowsd[ROWD_R * ny + j];
+        double cr = 0, ci = 0;
         for (int x = threadIdx.x; x < nx; x += blockDim.x) {
           const size_t q = (size_t)j * nx + x;
           const double ux = d.b.mom[n + q], uy = d.b.mom[2 * n + q];
           suy += uy * uy;
           mu = fmax(mu, sqrt(ux * ux + uy * uy));
           srho_c += r + d.b.mom[3 * n + q];
+          double sn, cs;
+          sincospi(2.0 * (double)x / (double)nx, &sn, &cs);
+          cr += uy * cs;
+          ci -= uy * sn;
         }
+        cr = block_sum(cr, red);
+        ci = block_sum(ci, red);
+        a1 = fmax(a1, sqrt(cr * cr + ci * ci) / (double)nx);
       }
       suy = block_sum(suy, red);
       srho_c = block_sum(srho_c, red);
       mu = block_max(mu, red);
       if (threadIdx.x == 0) {
-        double* h = d.hist + 4 * (size_t)row;
+        double* h = d.hist + kHistCols * (size_t)row;
         h[0] = (double)k;
         h[1] = sqrt(suy / (double)n);
         h[2] = mu;
         h[3] = srho_c;
+        h[4] = a1;
       }
     }
   }

@@ -17,6 +17,9 @@ OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, EBUSY = 0, 1, 2, 3, 4, 5
 FP64, FP32_DEV, FP32_DEV_F64MATH = 0, 1, 2
 INIT_NOISE, INIT_EQ29, INIT_REST = 0, 1, 2
 RATES_ANTISYMMETRIC, RATES_SYMMETRIC = 0, 1
+# columns of a batch history row: step, rms u_y, max |u|, sum of rho_c,
+# amplitude of the first x mode of u_y (lattice units)
+HIST_COLS = 5
 
 _PRECISION = {"fp64": FP64, "fp32": FP32_DEV, "fp32_dev": FP32_DEV, "fp32_f64math": FP32_DEV_F64MATH}
 _INIT = {"noise": INIT_NOISE, "eq29": INIT_EQ29, "rest": INIT_REST}
@@ -319,11 +322,12 @@ class Batch:
         return out
 
     def history(self, slot):
+        """The slot's history rows, shape (hist_rows, HIST_COLS); unused rows are zero."""
         import numpy as np
 
-        buf = (ctypes.c_double * (4 * self.hist_rows))()
+        buf = (ctypes.c_double * (HIST_COLS * self.hist_rows))()
         _check(lib().lbm_ec_batch_history(self._h, int(slot), buf, self.hist_rows))
-        return np.frombuffer(buf, dtype=np.float64).reshape(self.hist_rows, 4).copy()
+        return np.frombuffer(buf, dtype=np.float64).reshape(self.hist_rows, HIST_COLS).copy()
 
     def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_batch_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))

@@ -5,9 +5,11 @@ where perturbations stop decaying).
 Each instance is a channel of ny rows with nx the smallest 5-smooth length
 not below round(1.22 ny) (the aspect ratio 1.22 of the paper's domain), its
 own T and seed; all share C, M, Fe and the precision.  The growth rate of an
-instance is the least-squares slope of ln(rms u_y) against t / t0 (t0 =
-H^2 / K, the ionic time) over the second half of its run, from the rows the
-batch records every `emit_every` steps.
+instance is the least-squares slope of ln A1 against t / t0 (A1 the
+amplitude of the first x mode of u_y, the largest over the rows; t0 = H^2 / K,
+the ionic time) over the second half of its run, from the rows the batch
+records every `emit_every` steps.  (rms u_y would mix in the other modes,
+which decay at their own rates.)
 """
 
 import time
@@ -50,15 +52,16 @@ def ionic_time(cfg):
     return cfg["ny"] ** 2 / K
 
 
-def growth_rate(history, t0):
-    """Slope of ln(rms u_y) versus t / t0 over the second half of the rows."""
+def growth_rate(history, t0, col=4):
+    """Slope of ln(history[:, col]) versus t / t0 over the second half of the
+    rows (col 4: the first x mode of u_y)."""
     rows = history[history[:, 0] > 0]
     if len(rows) < 4:
         return float("nan")
     rows = rows[np.argsort(rows[:, 0])]
     h = len(rows) // 2
     t = rows[h:, 0] / t0
-    a = np.log(np.maximum(rows[h:, 1], 1e-300))
+    a = np.log(np.maximum(rows[h:, col], 1e-300))
     return float(np.polyfit(t, a, 1)[0])
 
 
