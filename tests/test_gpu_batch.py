@@ -95,6 +95,15 @@ def test_history_rows_match_fields():
     uy = f["uy"].cpu().numpy() * u0
     row = n // 10 - 1  # n = 60 is a multiple of 10
     assert math.isclose(h[row, 1], float(np.sqrt(np.mean(uy * uy))), rel_tol=1e-12)
+    a1 = float(np.max(np.abs(np.fft.fft(uy, axis=1)[:, 1])) / uy.shape[1])
+    assert math.isclose(h[row, 4], a1, rel_tol=1e-9)
+    # a negative row count is refused
+    import ctypes
+
+    from paper_1812_05711_amd.lbm_ec import EINVAL, HIST_COLS, lib
+
+    buf = (ctypes.c_double * HIST_COLS)()
+    assert lib().lbm_ec_batch_history(b._h, int(s), buf, -1) == EINVAL
     b.close()
 
 
