@@ -4,8 +4,9 @@ through lbm_ec_poisson, on seeded charge fields, up to the widest grids
 (nx = 2048 in FP64, 4096 in FP32 storage; a wider FP64 grid is refused).
 
 The y systems split into chunks of 32 rows; the cases give interface
-systems of 0 (one chunk), 1, 26, 127 and 512 interfaces (recursive
-doubling, 512 is its largest size) and 514 (serial block elimination).
+systems of 0 (one chunk), 1, 26, 127 and 256 interfaces (recursive
+doubling, 256 is its largest size) and 257 and 514 (serial block
+elimination).
 Tolerances: FP64 1e-11 relative to max |phi|; FP32 storage 1e-6 (the
 m >= 1 modes in FP32 arithmetic, the mean mode in FP64).
 """
@@ -21,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 BASE = dict(T=200.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6, noise_amp=1e-3,
             seed=181205711)
-CASES = [(16, 20), (24, 40), (40, 840), (8, 4096), (6, 16416), (6, 16480), (2048, 24), (4096, 24)]
+CASES = [(16, 20), (24, 40), (40, 840), (8, 4096), (6, 8224), (6, 8256), (6, 16480), (2048, 24), (4096, 24)]
 TOL = {"fp64": 1e-11, "fp32_f64math": 1e-6, "fp32": 1e-6}
 
 
