@@ -1582,12 +1582,16 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
       const size_t n = (size_t)ny * nx;
       // a1: the largest over the rows of |sum_x u_y exp(-2 pi i x / nx)| / nx,
       // the amplitude of the first x mode (the perturbation whose growth or
-      // decay marks the electroconvective threshold)
+      // decay marks the electroconvective threshold).  Rows go to the waves
+      // in turn; a wave reduces its row's mode with shuffles, the block then
+      // reduces the per-lane sums and maxima (fixed order for a fixed block
+      // size).
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
       double suy = 0, srho_c = 0, mu = 0, a1 = 0;
-      for (int j = 0; j < ny; ++j) {
+      for (int j = wave; j < ny; j += nw) {
         const double r = d.b.rowsd[ROWD_R * ny + j];
         double cr = 0, ci = 0;
-        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        for (int x = lane; x < nx; x += 64) {
           const size_t q = (size_t)j * nx + x;
           const double ux = d.b.mom[n + q], uy = d.b.mom[2 * n + q];
           suy += uy * uy;
@@ -1598,13 +1602,14 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
           cr += uy * cs;
           ci -= uy * sn;
         }
-        cr = block_sum(cr, red);
-        ci = block_sum(ci, red);
+        cr = wave_sum(cr);
+        ci = wave_sum(ci);
         a1 = fmax(a1, sqrt(cr * cr + ci * ci) / (double)nx);
       }
       suy = block_sum(suy, red);
       srho_c = block_sum(srho_c, red);
       mu = block_max(mu, red);
+      a1 = block_max(a1, red);
       if (threadIdx.x == 0) {
         double* h = d.hist + kHistCols * (size_t)row;
         h[0] = (double)k;
