@@ -280,9 +280,46 @@ template size_t collide_lds_bytes<double>(int);
 template size_t collide_lds_bytes<float>(int);
 
 // ------------------------------------------------------------- reductions
+// The value of lane (lane xor O) of a wave, O in {1, 2, 4, 8, 16, 32},
+// without the LDS crossbar: quad permutations (1, 2) and row shifts (4, 8)
+// of DPP, and the gfx950 row / half-wave swaps (16, 32).  The same values as
+// a xor shuffle.
+template <int O>
+__device__ __forceinline__ unsigned lane_xor(unsigned v) {
+  const int lane = threadIdx.x & 63;
+  if constexpr (O == 1) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (O == 2) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (O == 4 || O == 8) {
+    const unsigned up = (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x100 + O, 0xF, 0xF, false);  // row_shl:O
+    const unsigned dn = (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x110 + O, 0xF, 0xF, false);  // row_shr:O
+    return (lane & O) ? dn : up;
+  } else if constexpr (O == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return ((lane >> 4) & 1) ? r[0] : r[1];
+  } else {
+    static_assert(O == 32, "lane distance");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return lane >= 32 ? r[0] : r[1];
+  }
+}
+template <int O>
+__device__ __forceinline__ double lane_xor(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = lane_xor<O>((unsigned)u), hi = lane_xor<O>((unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Butterfly sum over the 64 lanes (distances 32, 16, ..., 1); every lane
+// gets the sum, in an order that depends only on the lane values.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += lane_xor<32>(v);
+  v += lane_xor<16>(v);
+  v += lane_xor<8>(v);
+  v += lane_xor<4>(v);
+  v += lane_xor<2>(v);
+  v += lane_xor<1>(v);
   return v;
 }
 
@@ -1376,8 +1413,12 @@ __global__ void __launch_bounds__(256) k_charge_in(Consts c, const double* __res
 // Maximum of v over the block (every thread gets it); `red` holds 16
 // doubles of LDS.
 __device__ double block_max(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  v = fmax(v, lane_xor<32>(v));
+  v = fmax(v, lane_xor<16>(v));
+  v = fmax(v, lane_xor<8>(v));
+  v = fmax(v, lane_xor<4>(v));
+  v = fmax(v, lane_xor<2>(v));
+  v = fmax(v, lane_xor<1>(v));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
   if (lane == 0) red[wave] = v;
