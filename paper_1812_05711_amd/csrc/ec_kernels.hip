@@ -455,16 +455,19 @@ __device__ __forceinline__ T charge_at(const Consts& c, const ChargeSrc<T>& q, i
 }
 
 // FP64 sums of the real and the imaginary parts of a[0 .. n) in an order
-// that does not depend on the block size (so launch shapes never change
-// results): 16 fixed segments, each summed by one wave with lane l taking
-// every 64th element of the segment, then the segments in order.  `red`
-// holds 32 doubles of LDS; thread 0 receives the sums.
-template <typename T>
+// that depends on n alone (so launch shapes never change results): nseg =
+// min(16, ceil(n / 64)) segments of ceil(n / nseg) elements, each summed by
+// one wave with lane l taking every 64th element of the segment, then the
+// segments in order.  `red` holds 32 doubles of LDS; thread 0 receives the
+// sums.  NSEG = 16 is the code for n >= 1024 (16 segments; fixed bounds),
+// NSEG = 0 the general one.
+template <typename T, int NSEG>
 __device__ __forceinline__ void row_sums_fixed_order(const C2<T>* __restrict__ a, int n, double* red, double& s0,
                                                      double& s1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int seg = (n + 15) / 16;
-  for (int q = wave; q < 16; q += nw) {
+  const int nseg = NSEG ? NSEG : min(16, (n + 63) / 64);
+  const int seg = (n + nseg - 1) / nseg;
+  for (int q = wave; q < nseg; q += nw) {
     const int lo = q * seg, hi = min(lo + seg, n);
     double p0 = 0.0, p1 = 0.0;
     for (int x = lo + lane; x < hi; x += 64) {
@@ -482,7 +485,7 @@ __device__ __forceinline__ void row_sums_fixed_order(const C2<T>* __restrict__ a
   s0 = 0.0;
   s1 = 0.0;
   if (threadIdx.x == 0) {
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < nseg; ++q) {
       s0 += red[q];
       s1 += red[16 + q];
     }
@@ -527,7 +530,10 @@ __device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>
   }
   __syncthreads();
   double s0, s1;
-  row_sums_fixed_order<T>(a, c.nx, red, s0, s1);
+  if (c.nx >= 1024)
+    row_sums_fixed_order<T, 16>(a, c.nx, red, s0, s1);
+  else
+    row_sums_fixed_order<T, 0>(a, c.nx, red, s0, s1);
   if (threadIdx.x == 0) {
     dcsum[j0] = s0;
     if (has1) dcsum[j1] = s1;
