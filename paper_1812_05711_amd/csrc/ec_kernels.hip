@@ -1523,16 +1523,20 @@ __global__ void __launch_bounds__(256) k_stats_final(Consts c, const double* __r
 // One launch per kernel type covers every slot of a batch; each block finds
 // its slot from the per-launch block offsets.
 
+// The last slot s < ns with off[s] <= b (offsets non-decreasing, off[0] =
+// 0; slots without blocks share their offset with the next one).  Every
+// wave compares 64 offsets at once and counts them with a ballot: one load
+// for ns <= 64, two (every 64th offset, then 64 of them) up to 4096 slots,
+// instead of a chain of dependent loads.  Called with all lanes active.
 __device__ __forceinline__ int find_slot(const int* __restrict__ off, int ns, int b) {
-  int lo = 0, hi = ns;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (off[mid] <= b)
-      lo = mid;
-    else
-      hi = mid;
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (ns > 64) {
+    const int i = lane * 64;
+    base = 64 * (__popcll(__ballot(i < ns && off[i] <= b)) - 1);
   }
-  return lo;
+  const int i = base + lane;
+  return base + __popcll(__ballot(i < ns && off[i] <= b)) - 1;
 }
 
 __device__ __forceinline__ bool slot_emits(const SlotDesc& d) {
