@@ -10,7 +10,7 @@ import hashlib
 import json
 import os
 
-FFT_THREADS = (128, 256, 512)
+FFT_THREADS = (64, 128, 256, 512)
 COLLIDE_SHAPES = ((64, 1), (128, 1), (256, 1), (512, 1), (1024, 1))
 DEFAULT = (256, 256, 1)
 
