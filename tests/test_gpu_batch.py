@@ -131,3 +131,33 @@ def test_admission_respects_workspace_and_reuse():
     for k in ref:
         assert np.array_equal(got[k], ref[k]), k
     b.close()
+
+
+def test_many_slots_equal_alone_bitwise():
+    """More slots than a wave has lanes (the block-to-slot search then runs on
+    two levels): 150 small slots of varied shapes and step counts, including
+    shapes whose chunk solves and interface systems have no blocks; a sample
+    across the whole slot range equals the same simulations run alone."""
+    from paper_1812_05711_amd.lbm_ec import Batch, batch_workspace_bytes, make_params
+
+    kws = []
+    for i in range(150):
+        nx = (2, 3, 8, 12, 17, 24)[i % 6]
+        ny = (6, 10, 16, 40, 70)[i % 5]
+        kws.append((dict(BASE, nx=nx, ny=ny, T=150.0 + i % 50, instance_id=i), 5 + i % 7))
+    ps = [make_params(precision="fp64", **kw) for kw, _ in kws]
+    ws = batch_workspace_bytes(ps, len(ps), 4) + (1 << 20)
+    b = Batch(len(ps), ws, precision="fp64", emit_every=0, hist_rows=4)
+    slots = [b.admit(n, **kw) for kw, n in kws]
+    assert None not in slots
+    b.step(20)
+    assert set(b.poll()) == set(slots)
+    for i in (0, 1, 63, 64, 65, 100, 127, 128, 149):
+        kw, n = kws[i]
+        assert b.steps_done(slots[i]) == n
+        got = {k: v.cpu().numpy() for k, v in b.fields(slots[i]).items()}
+        ref = _alone(kw, n, "fp64")
+        for k in ref:
+            assert np.all(np.isfinite(ref[k])), (i, k)
+            assert np.array_equal(got[k], ref[k]), (i, kw["nx"], kw["ny"], k)
+    b.close()
