@@ -25,7 +25,8 @@
  *     allocator, e.g. PyTorch); the library never allocates or frees device
  *     memory.  A handle owns only host memory.
  *   - Work is enqueued asynchronously on the caller's HIP stream given at
- *     creation; only lbm_ec_create and lbm_ec_stats wait for the stream.
+ *     creation; the calls that wait for the stream say so (lbm_ec_create,
+ *     lbm_ec_stats, the checkpoint calls and some batch calls).
  *   - Every int-returning call returns LBM_EC_OK (0) or an error code and
  *     leaves a message for lbm_ec_last_error() (thread-local).
  *   - Calls on one handle must not run concurrently from several threads.
@@ -108,7 +109,9 @@ typedef struct lbm_ec lbm_ec_t;
 int lbm_ec_params_default(lbm_ec_params* p);
 
 /* Checks a parameter set (see the field comments; also nx within the
- * x-transform limit of the chosen precision).  Returns OK or EINVAL. */
+ * widest grid of the chosen precision: 2048 in FP64, 4096 with FP32 storage,
+ * since a collide tile holds ten rows of nx values in LDS).  Returns OK or
+ * EINVAL. */
 int lbm_ec_validate(const lbm_ec_params* p);
 
 /* Device workspace bytes needed by lbm_ec_create for *p (0 if invalid). */
