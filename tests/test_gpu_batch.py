@@ -161,3 +161,29 @@ def test_many_slots_equal_alone_bitwise():
             assert np.all(np.isfinite(ref[k])), (i, k)
             assert np.array_equal(got[k], ref[k]), (i, kw["nx"], kw["ny"], k)
     b.close()
+
+
+def test_empty_batch_and_refused_arguments():
+    """Stepping and polling an empty batch does nothing; a precision other
+    than the batch's, a non-positive step count, more slots than the limit
+    and a release of a free slot are refused with EINVAL."""
+    from paper_1812_05711_amd.lbm_ec import EINVAL, Batch, LbmEcError, batch_workspace_bytes
+
+    b = Batch(4, batch_workspace_bytes([], 4, 8) + (1 << 20), precision="fp64", emit_every=0, hist_rows=8)
+    b.step(10)
+    assert b.poll() == []
+    kw = dict(BASE, nx=16, ny=12)
+    for bad in (dict(kw, precision="fp32"), dict(kw, nx=0)):
+        with pytest.raises(LbmEcError) as ei:
+            b.admit(5, **bad)
+        assert ei.value.code == EINVAL
+    with pytest.raises(LbmEcError) as ei:
+        b.admit(0, **kw)
+    assert ei.value.code == EINVAL
+    with pytest.raises(LbmEcError) as ei:
+        b.release(2)
+    assert ei.value.code == EINVAL
+    b.close()
+    with pytest.raises(LbmEcError) as ei:
+        Batch(5000, 1 << 20, precision="fp64")
+    assert ei.value.code == EINVAL
