@@ -111,3 +111,38 @@ def run_plain(configs, steps, device="cuda:0"):
         total += time.perf_counter() - t
         sim.close()
     return total
+
+
+def main(argv=None):
+    """Command line: runs the seeded T sweep as one batch and prints the
+    step time, the throughput and the growth rate of each instance."""
+    import argparse
+
+    ap = argparse.ArgumentParser(description="batched T sweep (one batch of uneven instances)")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--emit-every", type=int, default=100)
+    ap.add_argument("--precision", default="fp32_f64math", choices=["fp64", "fp32", "fp32_f64math"])
+    ap.add_argument("--tuning", default=None, help="fft_threads,collide_bx,collide_by (default: autotuned)")
+    args = ap.parse_args(argv)
+    cfgs = sweep_configs(n=args.instances, precision=args.precision)
+    tuning = (tuple(int(v) for v in args.tuning.split(",")) if args.tuning
+              else autotune.tune_batch(cfgs))
+    b, slots = make_batch(cfgs, args.steps, emit_every=args.emit_every, tuning=tuning)
+    b.stream.synchronize()
+    t = time.perf_counter()
+    b.step(args.steps)
+    b.stream.synchronize()
+    dt = time.perf_counter() - t
+    assert sorted(b.poll()) == sorted(slots)
+    nodes = sum(c["nx"] * c["ny"] for c in cfgs)
+    print(f"{len(cfgs)} instances, {nodes} nodes, {args.steps} steps, tuning {tuning}: "
+          f"{dt / args.steps * 1e6:.1f} us per step, {nodes * args.steps / dt / 1e6:.0f} MLUPS", flush=True)
+    for s, c in zip(slots, cfgs):
+        print(f"  ny {c['ny']:4d} nx {c['nx']:4d} T {c['T']:7.2f} growth rate "
+              f"{growth_rate(b.history(s), ionic_time(c)):+.4f}")
+    b.close()
+
+
+if __name__ == "__main__":
+    main()
