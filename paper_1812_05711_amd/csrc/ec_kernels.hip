@@ -1539,6 +1539,10 @@ __device__ __forceinline__ int find_slot(const int* __restrict__ off, int ns, in
   return base + __popcll(__ballot(i < ns && off[i] <= b)) - 1;
 }
 
+// Threads per block of the batched chunk solves: one wave, so that the few
+// (m, chunk) threads of small instances spread over more CUs.
+constexpr int kBatchTriThreads = 64;
+
 __device__ __forceinline__ bool slot_emits(const SlotDesc& d) {
   const long long k = d.steps_done + 1;  // the step being taken
   return k == d.steps_target || (d.emit_every > 0 && k % d.emit_every == 0);
@@ -1684,7 +1688,7 @@ int batch_blocks(const Consts& c, int k, const Tuning& tu) {
   switch (k) {
     case BK_FORWARD: return (c.ny + 1) / 2;
     case BK_INVERSE: return 1 + (c.ny + 1) / 2;  // block 0: the x-mean mode
-    case BK_TRI_LOCAL: return nm > 0 ? ((nm + 255) / 256) * c.NC : 0;
+    case BK_TRI_LOCAL: return nm > 0 ? ((nm + kBatchTriThreads - 1) / kBatchTriThreads) * c.NC : 0;
     case BK_TRI_REDUCED:
       if (nm <= 0 || c.NC < 2) return 0;
       return c.NC - 1 <= kScanMax ? (nm + 3) / 4 : (nm + 255) / 256;
@@ -1707,7 +1711,7 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
       hipLaunchKernelGGL((kb_forward<T, kFftPerThread>), dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s,
                          d_desc, d_off + BK_FORWARD * row, ns);
   if (totals[BK_TRI_LOCAL])
-    hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(256), 0, s, d_desc,
+    hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(kBatchTriThreads), 0, s, d_desc,
                        d_off + BK_TRI_LOCAL * row, ns);
   if (totals[BK_TRI_REDUCED])
     hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(256), 0, s, d_desc,
