@@ -187,14 +187,18 @@ int lbm_ec_save(lbm_ec_t* h, void* d_dst, size_t bytes);
 int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes);
 
 /* Kernel timing for measurement.  lbm_ec_profile_begin starts recording a
- * HIP event pair around every kernel the handle enqueues on its stream;
- * lbm_ec_profile_end stops, waits for the last event and returns, per kernel
+ * HIP event pair around every kernel of the classes whose bit is set in
+ * class_mask (bit k for class k) that the handle enqueues on its stream;
+ * lbm_ec_profile_end stops, waits for the stream and returns, per kernel
  * class, the summed elapsed milliseconds and the launch count in ms[k] and
- * launches[k] for k < n.  Classes: 0 forward transform (with the charge
- * gather), 1 y solves (the x-mean mode and the per-wavenumber systems),
- * 2 inverse transform, 3 collide-stream.  The events are created on first use and kept by the
+ * launches[k] for k < n.  Classes: 0 forward transform (with the tile edges
+ * of the charge density and the FP64 row sums), 1 y solves of the m >= 1
+ * modes (chunk solves and interface system), 2 inverse transform (with the
+ * x-mean mode), 3 collide-stream.  Each event pair adds a few microseconds
+ * to the step (the events carry no system-scope fence), so time only the
+ * classes needed.  The events are created on first use and kept by the
  * handle (host-side driver objects, no device memory). */
-int lbm_ec_profile_begin(lbm_ec_t* h);
+int lbm_ec_profile_begin(lbm_ec_t* h, uint32_t class_mask);
 int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 
 /* Launch shapes, which never change results: threads per x-transform block

@@ -175,6 +175,7 @@ enum { KC_FORWARD = 0, KC_TRIDIAG, KC_INVERSE, KC_COLLIDE, KC_COUNT };
 
 struct Profiler {
   bool on = false;
+  uint32_t mask = 0;           // kernel classes timed in the current window
   std::vector<hipEvent_t> ev;  // pool, reused across profiling windows
   std::vector<int> cls;        // class of each recorded pair
   size_t used = 0;             // events used in the current window
@@ -421,27 +422,30 @@ int setup(lbm_ec* h, unsigned char* ws) {
   return LBM_EC_OK;
 }
 
-// Records an event on the handle's stream when profiling (start of a pair
-// when `cls` >= 0, end of the open pair when `cls` < 0).
-int prof_mark(lbm_ec* h, int cls) {
+// Records an event on the handle's stream when class `cls` is being timed
+// (start of a pair when `end` is false, its end otherwise).
+int prof_mark(lbm_ec* h, int cls, bool end) {
   Profiler& P = h->prof;
-  if (!P.on) return LBM_EC_OK;
+  if (!P.on || !(P.mask & (1u << cls))) return LBM_EC_OK;
   if (P.used == P.ev.size()) {
+    // timing only: no system-scope fence (cache writeback and invalidation)
+    // around the kernels being timed; profile_end waits for the stream
+    // before it reads the times
     hipEvent_t e;
-    EC_HIP(hipEventCreate(&e));
+    EC_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     P.ev.push_back(e);
   }
-  if (cls >= 0) P.cls.push_back(cls);
+  if (!end) P.cls.push_back(cls);
   EC_HIP(hipEventRecord(P.ev[P.used++], h->s));
   return LBM_EC_OK;
 }
 
 #define EC_TIMED(h, cls, launch)           \
   do {                                     \
-    int rc_ = prof_mark((h), (cls));       \
+    int rc_ = prof_mark((h), (cls), false); \
     if (rc_) return rc_;                   \
     EC_HIP(launch);                        \
-    rc_ = prof_mark((h), -1);              \
+    rc_ = prof_mark((h), (cls), true);     \
     if (rc_) return rc_;                   \
   } while (0)
 
@@ -1036,9 +1040,10 @@ int lbm_ec_stats(lbm_ec_t* h, double* out) {
   return LBM_EC_OK;
 }
 
-int lbm_ec_profile_begin(lbm_ec_t* h) {
+int lbm_ec_profile_begin(lbm_ec_t* h, uint32_t class_mask) {
   if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
   h->prof.on = true;
+  h->prof.mask = class_mask;
   h->prof.used = 0;
   h->prof.cls.clear();
   return LBM_EC_OK;
@@ -1052,7 +1057,7 @@ int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n) {
     ms[k] = 0.0;
     launches[k] = 0;
   }
-  if (P.used) EC_HIP(hipEventSynchronize(P.ev[P.used - 1]));
+  EC_HIP(hipStreamSynchronize(h->s));
   for (size_t q = 0; q < P.cls.size(); ++q) {
     float t = 0.f;
     EC_HIP(hipEventElapsedTime(&t, P.ev[2 * q], P.ev[2 * q + 1]));

@@ -86,7 +86,7 @@ def lib():
     L.lbm_ec_poisson.restype = ctypes.c_int
     L.lbm_ec_stats.argtypes = [vp, dp]
     L.lbm_ec_stats.restype = ctypes.c_int
-    L.lbm_ec_profile_begin.argtypes = [vp]
+    L.lbm_ec_profile_begin.argtypes = [vp, ctypes.c_uint32]
     L.lbm_ec_profile_begin.restype = ctypes.c_int
     L.lbm_ec_profile_end.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
     L.lbm_ec_profile_end.restype = ctypes.c_int
@@ -234,8 +234,14 @@ class Simulation:
 
     KERNEL_CLASSES = ("forward", "tridiag", "inverse", "collide")
 
-    def profile_begin(self):
-        _check(lib().lbm_ec_profile_begin(self._h))
+    def profile_begin(self, classes=None):
+        """Times the kernel classes named in `classes` (default: all of
+        self.KERNEL_CLASSES) until profile_end."""
+        names = self.KERNEL_CLASSES if classes is None else classes
+        mask = 0
+        for c in names:
+            mask |= 1 << self.KERNEL_CLASSES.index(c)
+        _check(lib().lbm_ec_profile_begin(self._h, mask))
 
     def profile_end(self):
         """{class: (total_ms, launches)} since profile_begin (waits for the stream)."""
