@@ -1,0 +1,61 @@
+"""Host logic of the benchmark and the sweep (no GPU): the counter figure is
+used only for the kernel source it was taken on, --gpus N > 1 is refused
+with a message, the sweep's instance list is seeded and shaped as stated,
+and the growth-rate fit recovers a known exponential."""
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_traffic_figure_follows_the_kernel_source(tmp_path, monkeypatch):
+    import bench
+
+    # the committed summary matches the committed kernel source
+    assert bench.traffic_from_profiles(4096, 4096, "fp32_f64math") is not None
+    # another workload or another source hash gives no figure
+    assert bench.traffic_from_profiles(2048, 4096, "fp32_f64math") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.traffic_from_profiles(4096, 4096, "fp32_f64math") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_sweep_instances_are_seeded_and_shaped():
+    from paper_1812_05711_amd.sweep import five_smooth_at_least, sweep_configs
+
+    a, b = sweep_configs(), sweep_configs()
+    assert a == b and len(a) == 64
+    for c in a:
+        assert 64 <= c["ny"] <= 256 and 100.0 <= c["T"] <= 250.0
+        nx = c["nx"]
+        assert nx == five_smooth_at_least(round(1.22 * c["ny"]))
+        k = nx
+        for p in (2, 3, 5):
+            while k % p == 0:
+                k //= p
+        assert k == 1
+    assert len({c["instance_id"] for c in a}) == 64
+
+
+def test_growth_rate_fit():
+    from paper_1812_05711_amd.sweep import growth_rate
+
+    t0 = 1000.0
+    steps = np.arange(1, 41) * 50.0
+    hist = np.zeros((44, 5))
+    hist[:40, 0] = steps
+    hist[:40, 4] = 3e-4 * np.exp(0.7 * steps / t0)
+    hist[:40, 1] = 1.0  # another column, not used by the default fit
+    assert abs(growth_rate(hist, t0) - 0.7) < 1e-9
+    assert abs(growth_rate(hist, t0, col=1)) < 1e-12
