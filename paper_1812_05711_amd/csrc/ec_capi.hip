@@ -705,7 +705,7 @@ int rebuild(lbm_ec_batch* B) {
     B->fft8 = B->fft8 && ec::fft_in_place(sl.inst.plan, B->tu.fft_threads, 8);
     for (int k = 0; k < ec::BK_COUNT; ++k) {
       off[(size_t)k * (ns + 1) + q] = B->totals[k];
-      B->totals[k] += ec::batch_blocks(d.c, k, B->tu);
+      B->totals[k] += ec::batch_blocks(d.c, k);
     }
   }
   for (int k = 0; k < ec::BK_COUNT; ++k) off[(size_t)k * (ns + 1) + ns] = B->totals[k];

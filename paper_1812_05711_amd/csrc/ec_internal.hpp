@@ -168,8 +168,9 @@ struct Tuning {
 // Batched kernels; slot s owns the blocks [off[k][s], off[k][s+1]) of launch k.
 enum BatchKernel { BK_FORWARD = 0, BK_TRI_LOCAL, BK_TRI_REDUCED, BK_INVERSE, BK_COLLIDE, BK_STATS, BK_COUNT };
 
-// Blocks that kernel k uses for one instance.
-int batch_blocks(const Consts& c, int k, const Tuning& tu);
+// Blocks that kernel k uses for one instance (independent of the launch
+// shapes, so that a block-to-slot table never depends on the tuning).
+int batch_blocks(const Consts& c, int k);
 
 // Enqueues one batched step (all kernels, then the device-side advance) for
 // ns slots.  d_off holds BK_COUNT rows of ns + 1 offsets; totals[k] is the

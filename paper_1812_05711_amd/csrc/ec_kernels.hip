@@ -1683,7 +1683,7 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
   }
 }
 
-int batch_blocks(const Consts& c, int k, const Tuning& tu) {
+int batch_blocks(const Consts& c, int k) {
   const int nm = c.M - 1;
   switch (k) {
     case BK_FORWARD: return (c.ny + 1) / 2;
@@ -1703,26 +1703,28 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
                              size_t collide_lds, bool fft8, const Tuning& tu, hipStream_t s) {
   const int row = ns + 1;
   SlotDesc* D = const_cast<SlotDesc*>(d_desc);
-  if (totals[BK_FORWARD])
+  if (totals[BK_FORWARD]) {
     if (fft8)
       hipLaunchKernelGGL((kb_forward<T, 8>), dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s, d_desc,
                          d_off + BK_FORWARD * row, ns);
     else
       hipLaunchKernelGGL((kb_forward<T, kFftPerThread>), dim3(totals[BK_FORWARD]), dim3(tu.fft_threads), lds, s,
                          d_desc, d_off + BK_FORWARD * row, ns);
+  }
   if (totals[BK_TRI_LOCAL])
     hipLaunchKernelGGL(kb_tri_local<T>, dim3(totals[BK_TRI_LOCAL]), dim3(kBatchTriThreads), 0, s, d_desc,
                        d_off + BK_TRI_LOCAL * row, ns);
   if (totals[BK_TRI_REDUCED])
     hipLaunchKernelGGL(kb_tri_reduced<T>, dim3(totals[BK_TRI_REDUCED]), dim3(256), 0, s, d_desc,
                        d_off + BK_TRI_REDUCED * row, ns);
-  if (totals[BK_INVERSE])
+  if (totals[BK_INVERSE]) {
     if (fft8)
       hipLaunchKernelGGL((kb_inverse<T, 8>), dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s, d_desc,
                          d_off + BK_INVERSE * row, ns);
     else
       hipLaunchKernelGGL((kb_inverse<T, kFftPerThread>), dim3(totals[BK_INVERSE]), dim3(tu.fft_threads), lds, s,
                          d_desc, d_off + BK_INVERSE * row, ns);
+  }
   if (totals[BK_COLLIDE])
     hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(tu.cbx * tu.cby), collide_lds, s, d_desc,
                        d_off + BK_COLLIDE * row, ns);
@@ -1739,10 +1741,6 @@ template hipError_t launch_batch_step<float, double>(const SlotDesc*, const int*
                                                     const Tuning&, hipStream_t);
 
 // ------------------------------------------------------------- launchers
-static inline dim3 node_grid2(const Consts& c, dim3 blk) {
-  return dim3((c.nx + blk.x - 1) / blk.x, (c.ny + blk.y - 1) / blk.y);
-}
-
 template <typename T>
 hipError_t launch_init_charge(const Consts& c, const Bufs& b, hipStream_t s) {
   dim3 blk(256), grd((c.nx + 255) / 256, c.ny);
