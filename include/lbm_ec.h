@@ -238,10 +238,12 @@ size_t lbm_ec_batch_workspace_bytes(const lbm_ec_params* ps, int32_t n, int32_t 
  * precision: one of LBM_EC_FP64 / FP32_DEV / FP32_DEV_F64MATH for all slots.
  * emit_every: every emit_every steps (0 = never) and at its last step each
  * slot writes its moments and a history row {step, rms u_y, max |u|, sum of
- * rho_c, A1} (lattice units), A1 the largest over the rows of
+ * rho_c, A1, unhealthy} (lattice units), A1 the largest over the rows of
  * |sum_x u_y(x) exp(-2 pi i x / nx)| / nx: the amplitude of the first x mode
  * of u_y, whose growth or decay in time locates the electroconvective
- * threshold (the linear stability test of section V).  hip_stream: stream for all batch work; NULL makes
+ * threshold (the linear stability test of section V); unhealthy the number
+ * of nodes with non-finite moments or rho <= 0 (the health check of
+ * lbm_ec_stats, per slot).  hip_stream: stream for all batch work; NULL makes
  * the batch create its own (graphs cannot be captured on the null stream).
  * Errors: EINVAL, ENOMEM, EHIP. */
 int lbm_ec_batch_create(int32_t max_slots, int32_t precision, int32_t emit_every, int32_t hist_rows, void* d_ws,
@@ -269,7 +271,7 @@ int64_t lbm_ec_batch_steps_done(lbm_ec_batch_t* b, int32_t slot);
 int lbm_ec_batch_fields(lbm_ec_batch_t* b, int32_t slot, double* rho, double* ux, double* uy, double* rho_c,
                         double* phi);
 
-/* Copies the first `rows` history rows of a slot (5 doubles each, host
+/* Copies the first `rows` history rows of a slot (6 doubles each, host
  * memory); waits for the stream.  Row r holds step (r+1) * emit_every, the
  * last row the final step when that is not a multiple of emit_every; unused
  * rows are zero. */
@@ -287,6 +289,14 @@ size_t lbm_ec_batch_free_bytes(lbm_ec_batch_t* b);
 
 /* Releases the batch (waits for its stream; the caller frees the workspace). */
 void lbm_ec_batch_destroy(lbm_ec_batch_t* b);
+
+/* Test hooks of the failure detection, for callers that test it: a NaN is
+ * written into one population of the current state of an instance (or of a
+ * batch slot), so that its next steps fail the health check while other
+ * instances and slots are unaffected.  Wait for the stream.  EINVAL for a
+ * NULL handle or a free slot. */
+int lbm_ec_debug_poison(lbm_ec_t* h);
+int lbm_ec_batch_debug_poison(lbm_ec_batch_t* b, int32_t slot);
 
 /* Message of the last error on this thread ("" if none). */
 const char* lbm_ec_last_error(void);

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -1194,6 +1195,31 @@ int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes) {
   EC_HIP(hipMemcpyAsync(h->b.mom, d + K.off_mom, K.mom, hipMemcpyDeviceToDevice, h->s));
   h->steps = H.steps;
   return LBM_EC_OK;
+}
+
+// Test hook of the failure detection: a NaN in one population of the current
+// state (population 0 of node (0, 0)).  Waits for the stream.
+namespace {
+int poison_instance(lbm_ec* h) {
+  static const float kNanF = std::numeric_limits<float>::quiet_NaN();
+  static const double kNanD = std::numeric_limits<double>::quiet_NaN();
+  const void* src = h->fp32 ? (const void*)&kNanF : (const void*)&kNanD;
+  EC_HIP(hipMemcpyAsync(h->b.f[h->cur], src, h->L.tsize, hipMemcpyHostToDevice, h->s));
+  EC_HIP(hipStreamSynchronize(h->s));
+  return LBM_EC_OK;
+}
+}  // namespace
+
+int lbm_ec_debug_poison(lbm_ec_t* h) {
+  if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
+  return poison_instance(h);
+}
+
+int lbm_ec_batch_debug_poison(lbm_ec_batch_t* B, int32_t slot) {
+  if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
+  int rc = pull_state(B);  // the slot's current buffer is kept on the device
+  if (rc) return rc;
+  return poison_instance(&B->slots[slot].inst);
 }
 
 void lbm_ec_destroy(lbm_ec_t* h) {

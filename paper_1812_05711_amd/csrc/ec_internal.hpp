@@ -40,8 +40,9 @@ __host__ __device__ inline int tile_rows(int ny) { return ny >= 512 ? (ny / 256 
 constexpr int kStatsBands = 1024;
 
 // Doubles per row of a batch slot's diagnostics history: step, rms u_y,
-// max |u|, sum of rho_c, amplitude of the first x mode of u_y (lattice units).
-constexpr int kHistCols = 5;
+// max |u|, sum of rho_c, amplitude of the first x mode of u_y (lattice
+// units), number of unhealthy nodes (non-finite moments or rho <= 0).
+constexpr int kHistCols = 6;
 
 // Rows per chunk of the partitioned per-wavenumber solves.
 constexpr int kChunk = 32;

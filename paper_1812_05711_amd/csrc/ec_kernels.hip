@@ -1642,16 +1642,18 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
       // reduces the per-lane sums and maxima (fixed order for a fixed block
       // size).
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-      double suy = 0, srho_c = 0, mu = 0, a1 = 0;
+      double suy = 0, srho_c = 0, mu = 0, a1 = 0, bad = 0;
       for (int j = wave; j < ny; j += nw) {
-        const double r = d.b.rowsd[ROWD_R * ny + j];
+        const double r = d.b.rowsd[ROWD_R * ny + j], rr = d.b.rowsd[ROWD_RHO_REF * ny + j];
         double cr = 0, ci = 0;
         for (int x = lane; x < nx; x += 64) {
           const size_t q = (size_t)j * nx + x;
           const double ux = d.b.mom[n + q], uy = d.b.mom[2 * n + q];
+          const double rho = rr + d.b.mom[q], rc = r + d.b.mom[3 * n + q];
           suy += uy * uy;
           mu = fmax(mu, sqrt(ux * ux + uy * uy));
-          srho_c += r + d.b.mom[3 * n + q];
+          srho_c += rc;
+          if (!(rho > 0.0) || !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(rc)) bad += 1.0;
           double sn, cs;
           sincospi(2.0 * (double)x / (double)nx, &sn, &cs);
           cr += uy * cs;
@@ -1665,6 +1667,7 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
       srho_c = block_sum(srho_c, red);
       mu = block_max(mu, red);
       a1 = block_max(a1, red);
+      bad = block_sum(bad, red);
       if (threadIdx.x == 0) {
         double* h = d.hist + kHistCols * (size_t)row;
         h[0] = (double)k;
@@ -1672,6 +1675,7 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
         h[2] = mu;
         h[3] = srho_c;
         h[4] = a1;
+        h[5] = bad;
       }
     }
   }

@@ -18,8 +18,8 @@ FP64, FP32_DEV, FP32_DEV_F64MATH = 0, 1, 2
 INIT_NOISE, INIT_EQ29, INIT_REST = 0, 1, 2
 RATES_ANTISYMMETRIC, RATES_SYMMETRIC = 0, 1
 # columns of a batch history row: step, rms u_y, max |u|, sum of rho_c,
-# amplitude of the first x mode of u_y (lattice units)
-HIST_COLS = 5
+# amplitude of the first x mode of u_y (lattice units), unhealthy nodes
+HIST_COLS = 6
 
 _PRECISION = {"fp64": FP64, "fp32": FP32_DEV, "fp32_dev": FP32_DEV, "fp32_f64math": FP32_DEV_F64MATH}
 _INIT = {"noise": INIT_NOISE, "eq29": INIT_EQ29, "rest": INIT_REST}
@@ -123,6 +123,10 @@ def lib():
     L.lbm_ec_set_tuning.restype = ctypes.c_int
     L.lbm_ec_batch_set_tuning.argtypes = [vp, i32, i32, i32]
     L.lbm_ec_batch_set_tuning.restype = ctypes.c_int
+    L.lbm_ec_debug_poison.argtypes = [vp]
+    L.lbm_ec_debug_poison.restype = ctypes.c_int
+    L.lbm_ec_batch_debug_poison.argtypes = [vp, i32]
+    L.lbm_ec_batch_debug_poison.restype = ctypes.c_int
     L.lbm_ec_destroy.argtypes = [vp]
     L.lbm_ec_destroy.restype = None
     L.lbm_ec_last_error.argtypes = []
@@ -218,6 +222,10 @@ class Simulation:
 
     def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+
+    def debug_poison(self):
+        """Test hook: a NaN into one population of the current state."""
+        _check(lib().lbm_ec_debug_poison(self._h))
 
     def save(self) -> torch.Tensor:
         """Checkpoint of the current state in a new device uint8 tensor."""
@@ -337,6 +345,10 @@ class Batch:
 
     def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_batch_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+
+    def debug_poison(self, slot):
+        """Test hook: a NaN into one population of the slot's current state."""
+        _check(lib().lbm_ec_batch_debug_poison(self._h, int(slot)))
 
     def release(self, slot):
         _check(lib().lbm_ec_batch_release(self._h, int(slot)))

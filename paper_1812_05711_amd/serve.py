@@ -63,9 +63,13 @@ class BatchBackend:
         return self.batch.poll()
 
     def finish(self, slot, req):
+        """Releases a finished slot; returns the health of its final state
+        (no non-finite moments, rho > 0) from the slot's last history row."""
         if req["id"] in self.keep:
             self.kept[req["id"]] = {k: v.cpu().numpy() for k, v in self.batch.fields(slot).items()}
+        healthy = bool(self.batch.history(slot)[-1, 5] == 0)
         self.batch.release(slot)
+        return {"healthy": healthy}
 
     def close(self):
         self.batch.close()
@@ -101,10 +105,10 @@ def serve(requests, backend, chunk=100, warmup=0, clock=time.perf_counter, sleep
             t_done = clock() - t0
             for slot in done:
                 req = running.pop(slot)
-                backend.finish(slot, req)
+                extra = backend.finish(slot, req) or {}
                 records.append(dict(id=req["id"], arrival=req["arrival"], admitted=req["admitted"], done=t_done,
                                     latency=t_done - req["arrival"], nodes=req["params"]["nx"] * req["params"]["ny"],
-                                    steps=req["steps"]))
+                                    steps=req["steps"], **extra))
         elif pending:
             sleep(max(0.0, pending[0]["arrival"] - (clock() - t0)))
     wall = clock() - t0
@@ -114,5 +118,6 @@ def serve(requests, backend, chunk=100, warmup=0, clock=time.perf_counter, sleep
                    p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
                    p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
                    mean_s=float(lat.mean()) if len(lat) else None,
-                   mlups=node_steps / wall / 1e6, max_queue=queued_max)
+                   mlups=node_steps / wall / 1e6, max_queue=queued_max,
+                   unhealthy=sum(1 for r in records if r.get("healthy") is False))
     return records, summary
