@@ -16,12 +16,23 @@ sys.path.insert(0, ROOT)
 def test_traffic_figure_follows_the_kernel_source(tmp_path, monkeypatch):
     import bench
 
-    # the committed summary matches the committed kernel source
-    assert bench.traffic_from_profiles(4096, 4096, "fp32_f64math") is not None
-    # another workload or another source hash gives no figure
-    assert bench.traffic_from_profiles(2048, 4096, "fp32_f64math") is None
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.traffic_from_profiles(4096, 4096, "fp32_f64math") is None
+    def write(h):
+        d = tmp_path / "profiles"
+        d.mkdir(exist_ok=True)
+        (d / "collide_64x32_fp32_hbm_counters.md").write_text(
+            "# counters\n\n| a | b |\n\n```\ntraffic_bytes_per_launch: 12345\n"
+            f"source_hash: {h}\nnx: 64\nny: 32\nprecision: fp32\n```\n")
+
+    current = bench.kernel_source_hash()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: current)
+    assert bench.traffic_from_profiles(64, 32, "fp32") is None  # no summary
+    write(current)
+    assert bench.traffic_from_profiles(64, 32, "fp32") == 12345.0
+    # another workload, or counters taken on another kernel source: no figure
+    assert bench.traffic_from_profiles(64, 64, "fp32") is None
+    write("0" * 16)
+    assert bench.traffic_from_profiles(64, 32, "fp32") is None
 
 
 def test_more_than_one_gpu_is_refused():
