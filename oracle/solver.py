@@ -15,10 +15,12 @@ n -> n+1, in the order the paper's equations give it:
   6. streaming with the electrode conditions of Table I.
 """
 
+import dataclasses
+
 import numpy as np
 
-from . import hydrostatic, lbm, poisson, splitmix
-from .lattice import WI, Params, lattice_constants
+from . import diagnostics, hydrostatic, lbm, poisson, splitmix
+from .lattice import CI, WI, Params, lattice_constants
 
 
 def round_bits(v, bits=40):
@@ -76,16 +78,8 @@ class Oracle:
         nx, ny = p.nx, p.ny
         self.n = 0
         self.bx = float(p.body_force_x)
-        if p.init_mode == "rest":
-            rho_c_ref, s_ref = np.zeros(ny), 0.0
-        else:
-            rho_c_ref, s_ref = hydrostatic_rows(p, lc)
-        # reference rows, rounded so that w_i times them is exact (see lbm.py)
-        self.s_ref = 36.0 * float(round_bits(s_ref / 36.0))
-        self.rho_ref = 1.0 + self.s_ref * ((np.arange(ny) + 0.5) - 0.5 * lc.H)
-        q = round_bits(rho_c_ref / 36.0)
-        self.r = 36.0 * q  # reference charge row
-        self.R = (36.0 * WI)[:, None] * q[None, :]  # R_i(y) = w_i r(y), exact
+        self.pending_T = None
+        rho_c_ref = self._set_reference_rows(p, lc)
         if p.init_mode == "rest":
             self.ft = np.zeros((9, ny, nx))
             self.gt = np.zeros((9, ny, nx))
@@ -140,10 +134,79 @@ class Oracle:
         for _ in range(n):
             m = self.macroscopic()
             ft_post, gt_post = self.collide(m)
+            if self.pending_T is not None:
+                ft_post, gt_post = self._continue_at(self.pending_T, ft_post, gt_post)
+                self.pending_T = None
             self.ft = lbm.stream_fluid(ft_post, self.s_ref)
             self.gt = lbm.stream_charge(gt_post, self.R, self.lc.rho0)
             self.n += 1
         return self
+
+    # ---- reference rows and continuation at another T ----------------------
+    def _set_reference_rows(self, p: Params, lc):
+        """Reference rows of parameters p, rounded so that w_i times them is
+        exact (see lbm.py); returns the unrounded closed-form charge row."""
+        ny = p.ny
+        if p.init_mode == "rest":
+            rho_c_ref, s_ref = np.zeros(ny), 0.0
+        else:
+            rho_c_ref, s_ref = hydrostatic_rows(p, lc)
+        self.s_ref = 36.0 * float(round_bits(s_ref / 36.0))
+        self.rho_ref = 1.0 + self.s_ref * ((np.arange(ny) + 0.5) - 0.5 * lc.H)
+        q = round_bits(rho_c_ref / 36.0)
+        self.r = 36.0 * q  # reference charge row
+        self.R = (36.0 * WI)[:, None] * q[None, :]  # R_i(y) = w_i r(y), exact
+        return rho_c_ref
+
+    def set_T(self, T: float):
+        """Continue the run at electric Rayleigh number T (the continuation of
+        section V.2, where T is lowered after the vortices have formed).
+
+        The paper does not say what carries over when T changes.  Reading:
+        the change happens between the collision of the next step and its
+        streaming, and the state keeps its nondimensional meaning --
+          charge: the full post-collision populations are scaled by
+            eps_new / eps_old, so rho_c / rho0 (rho_c in units of eps / H^2)
+            and the field E are continuous;
+          fluid: the departure of the post-collision populations from the
+            hydrostatic state of the lattice is kept.  That state has
+            rho_ref(y) and the uniform force s_ref / 3 in y; its pre-collision
+            populations w_i (rho_ref - c_iy s_ref / 2) carry the momentum
+            -F / 2 that makes u = 0 (Eq. 7), and the source of Eq. 12 adds F,
+            so its post-collision populations are w_i (rho_ref + c_iy s_ref / 2).
+        Everything derived from T (K, eps, rho0, D_c, the charge rates, the
+        reference rows) is that of the new T from the streaming on.
+        """
+        lattice_constants(dataclasses.replace(self.p, T=float(T)))  # validates
+        self.pending_T = float(T)
+        return self
+
+    def _continue_at(self, T, ft_post, gt_post):
+        p_new = dataclasses.replace(self.p, T=T)
+        lc_new = lattice_constants(p_new)
+        scale = lc_new.eps / self.lc.eps
+        R_old, s_old = self.R, self.s_ref
+        self._set_reference_rows(p_new, lc_new)
+        # g_new = scale (R_old + gt_post) - R_new, grouped so that the large
+        # reference rows cancel first
+        gt_new = scale * gt_post + (scale * R_old - self.R)[:, :, None]
+        # ft is relative to w_i rho_ref(y): keeping f - w_i (rho_ref + c_iy s/2)
+        # shifts it by w_i c_iy (s_new - s_old) / 2
+        ft_new = ft_post + (WI * CI[:, 1])[:, None, None] * (0.5 * (self.s_ref - s_old))
+        self.p, self.lc = p_new, lc_new
+        return ft_new, gt_new
+
+    def electrode_currents(self):
+        """(injector, collector) currents of the current state: the charge
+        that the next streaming brings in through the injector and takes out
+        through the collector, in lattice units per step, summed over x.  The
+        collector one is the cathode current I of the electric Nusselt number
+        Ne_0 = I / I_0 (section V.2)."""
+        m = self.macroscopic()
+        _, gt_post = self.collide(m)
+        g_post = gt_post + self.R[:, :, None]
+        lower, upper = diagnostics.charge_boundary_fluxes(g_post, self.lc.rho0)
+        return lower, -upper
 
     # ---- full populations (diagnostics and tests) --------------------------
     def full(self, ft, gt):
