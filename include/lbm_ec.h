@@ -186,6 +186,24 @@ size_t lbm_ec_checkpoint_bytes(const lbm_ec_t* h);
 int lbm_ec_save(lbm_ec_t* h, void* d_dst, size_t bytes);
 int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes);
 
+/* Continuation at another electric Rayleigh number T (section V.2: T is
+ * lowered after the vortices have formed, and they persist down to T_f).  The
+ * change takes effect between the last collision and the next streaming; what
+ * carries over, where the paper does not say: the charge keeps its
+ * nondimensional value (the post-collision charge populations, in full, are
+ * scaled by eps_new / eps_old, eps = (M K)^2 the lattice permittivity, so
+ * rho_c / rho0 and E are continuous), and the fluid populations keep their
+ * departure from the hydrostatic state of the lattice (the stored deviations
+ * are unchanged; the reference density row and the reference force become
+ * those of the new T).  K, eps, rho0, D_c, the charge rates and the injector
+ * constants are those of T from the next step on; the step count is kept.
+ * The moments that lbm_ec_fields reads are re-expressed in the new units
+ * (charge scaled; density deviation and velocity in lattice units kept).
+ * Waits for the stream.  EINVAL for a T that lbm_ec_validate refuses (the
+ * instance is then unchanged).  A checkpoint records T: lbm_ec_load refuses
+ * one taken at another T. */
+int lbm_ec_set_T(lbm_ec_t* h, double T);
+
 /* Kernel timing for measurement.  lbm_ec_profile_begin starts recording a
  * HIP event pair around every kernel of the classes whose bit is set in
  * class_mask (bit k for class k) that the handle enqueues on its stream;
@@ -238,12 +256,15 @@ size_t lbm_ec_batch_workspace_bytes(const lbm_ec_params* ps, int32_t n, int32_t 
  * precision: one of LBM_EC_FP64 / FP32_DEV / FP32_DEV_F64MATH for all slots.
  * emit_every: every emit_every steps (0 = never) and at its last step each
  * slot writes its moments and a history row {step, rms u_y, max |u|, sum of
- * rho_c, A1, unhealthy} (lattice units), A1 the largest over the rows of
+ * rho_c, A1, unhealthy, I} (lattice units), A1 the largest over the rows of
  * |sum_x u_y(x) exp(-2 pi i x / nx)| / nx: the amplitude of the first x mode
  * of u_y, whose growth or decay in time locates the electroconvective
  * threshold (the linear stability test of section V); unhealthy the number
  * of nodes with non-finite moments or rho <= 0 (the health check of
- * lbm_ec_stats, per slot).  hip_stream: stream for all batch work; NULL makes
+ * lbm_ec_stats, per slot); I the collector current, the charge that the next
+ * streaming takes out through the upper electrode (-out[9] of lbm_ec_stats),
+ * the cathode current of the electric Nusselt number Ne_0 = I / I_0 of
+ * section V.2.  hip_stream: stream for all batch work; NULL makes
  * the batch create its own (graphs cannot be captured on the null stream).
  * Errors: EINVAL, ENOMEM, EHIP. */
 int lbm_ec_batch_create(int32_t max_slots, int32_t precision, int32_t emit_every, int32_t hist_rows, void* d_ws,
@@ -271,11 +292,16 @@ int64_t lbm_ec_batch_steps_done(lbm_ec_batch_t* b, int32_t slot);
 int lbm_ec_batch_fields(lbm_ec_batch_t* b, int32_t slot, double* rho, double* ux, double* uy, double* rho_c,
                         double* phi);
 
-/* Copies the first `rows` history rows of a slot (6 doubles each, host
+/* Copies the first `rows` history rows of a slot (7 doubles each, host
  * memory); waits for the stream.  Row r holds step (r+1) * emit_every, the
  * last row the final step when that is not a multiple of emit_every; unused
  * rows are zero. */
 int lbm_ec_batch_history(lbm_ec_batch_t* b, int32_t slot, double* out, int32_t rows);
+
+/* lbm_ec_set_T for one slot of a batch, at the step the slot has reached
+ * (waits for the stream).  The slot keeps its step count and target; the
+ * batch re-captures its graphs at the next step. */
+int lbm_ec_batch_set_T(lbm_ec_batch_t* b, int32_t slot, double T);
 
 /* Launch shapes for the batch's kernels (as lbm_ec_set_tuning); the graphs
  * are re-captured at the next step. */

@@ -198,10 +198,59 @@ struct lbm_ec {
 
 namespace {
 
+// Reference rows: the closed-form hydrostatic charge profile r(j) and the
+// linear density profile balancing its uniform force; rounded to `bits`
+// significant bits so that w_i times them, and their differences between
+// rows, are exact in the storage type.
+struct RefRows {
+  std::vector<double> rc_closed, q, rho_ref;  // q = r / 36
+  double s_ref = 0.0, s_init = 0.0;
+};
+
+RefRows reference_rows(const lbm_ec_params& p, double eps, int bits) {
+  const int ny = p.ny;
+  const double H = (double)ny;
+  RefRows R;
+  R.rc_closed.assign(ny, 0.0);
+  R.q.resize(ny);
+  R.rho_ref.resize(ny);
+  double s_ref = 0.0;
+  if (p.init_mode != LBM_EC_INIT_REST) {
+    const double e0 = field_at_injector(p.C);
+    for (int j = 0; j < ny; ++j) {
+      const double y = ((double)j + 0.5) / (double)ny;
+      double rc_nd = 0.0;
+      if (p.C != 0.0) {
+        const double e2 = e0 * e0 + 2.0 * p.C * e0 * y;
+        rc_nd = p.C * e0 / std::sqrt(e2);
+      }
+      R.rc_closed[j] = eps / (H * H) * rc_nd;
+    }
+    const double F0 = eps * p.C * e0 / std::pow(H, 3.0);
+    s_ref = 3.0 * F0;
+  }
+  R.s_init = 36.0 * round_bits(s_ref / 36.0, 40);
+  R.s_ref = 36.0 * round_bits(s_ref / 36.0, bits);
+  for (int j = 0; j < ny; ++j) {
+    R.q[j] = round_bits(R.rc_closed[j] / 36.0, bits);
+    R.rho_ref[j] = 1.0 + R.s_ref * (((double)j + 0.5) - 0.5 * H);
+  }
+  return R;
+}
+
+double lattice_eps(const lbm_ec_params& p) {
+  const double nu = kCs2 * (p.tau_plus - 0.5);
+  const double K = nu * p.T / (p.M * p.M);
+  return (p.M * K) * (p.M * K);
+}
+
 // Lattice constants (Eq. 16-17, Eq. 26 with rho = 1, dphi0 = 1, H = ny) and
-// all tables, written into host vectors then copied to the device.
+// all tables, written into host vectors then copied to the device.  fresh:
+// a new instance (the potential, the spectrum and the moments are cleared);
+// otherwise only what the parameters fix is rewritten, and the state, the
+// potential and the rows each step writes are left as they are.
 template <typename T>
-int setup(lbm_ec* h, unsigned char* ws) {
+int setup(lbm_ec* h, unsigned char* ws, bool fresh = true) {
   const lbm_ec_params& p = h->p;
   const Layout& L = h->L;
   const int nx = p.nx, ny = p.ny;
@@ -244,34 +293,12 @@ int setup(lbm_ec* h, unsigned char* ws) {
   c.noise_amp = p.noise_amp;
   c.seed = p.seed + (uint64_t)(int64_t)p.instance_id;
 
-  // reference rows: closed-form hydrostatic charge profile r(j) and the
-  // linear density profile balancing its uniform force; rounded so that
-  // w_i times them, and their differences between rows, are exact in T.
-  const bool rest = p.init_mode == LBM_EC_INIT_REST;
-  const int bits = sizeof(T) == 8 ? 40 : 18;
-  const double e0 = field_at_injector(p.C);
-  std::vector<double> rc_closed(ny, 0.0);
-  double s_ref = 0.0;
-  if (!rest) {
-    for (int j = 0; j < ny; ++j) {
-      const double y = ((double)j + 0.5) / (double)ny;
-      double rc_nd = 0.0;
-      if (p.C != 0.0) {
-        const double e2 = e0 * e0 + 2.0 * p.C * e0 * y;
-        rc_nd = p.C * e0 / std::sqrt(e2);
-      }
-      rc_closed[j] = eps / (H * H) * rc_nd;
-    }
-    const double F0 = eps * p.C * e0 / std::pow(H, 3.0);
-    s_ref = 3.0 * F0;
-  }
-  c.s_init = 36.0 * round_bits(s_ref / 36.0, 40);
-  s_ref = 36.0 * round_bits(s_ref / 36.0, bits);
-  std::vector<double> q(ny), rho_ref(ny);
-  for (int j = 0; j < ny; ++j) {
-    q[j] = round_bits(rc_closed[j] / 36.0, bits);
-    rho_ref[j] = 1.0 + s_ref * (((double)j + 0.5) - 0.5 * H);
-  }
+  const RefRows ref = reference_rows(p, eps, sizeof(T) == 8 ? 40 : 18);
+  const std::vector<double>& rc_closed = ref.rc_closed;
+  const std::vector<double>& q = ref.q;
+  const std::vector<double>& rho_ref = ref.rho_ref;
+  const double s_ref = ref.s_ref;
+  c.s_init = ref.s_init;
   const double wa = 1.0 / 9.0, wd = 1.0 / 36.0;
   c.s_ref = s_ref;
   // R_axis = 4 q, R_diag = q (36 w_i is exactly 4 and 1)
@@ -410,15 +437,21 @@ int setup(lbm_ec* h, unsigned char* ws) {
     }
   }
   EC_HIP(hipMemcpyAsync(h->b.rows, rows.data(), rows.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
-  EC_HIP(hipMemcpyAsync(h->b.rowsd, rowsd.data(), rowsd.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
+  // rows 0 .. ROWD_RC_CLOSED are fixed by the parameters, the others are
+  // written by the steps
+  EC_HIP(hipMemcpyAsync(h->b.rowsd, rowsd.data(),
+                        (fresh ? rowsd.size() : (size_t)(ec::ROWD_RC_CLOSED + 1) * ny) * sizeof(double),
+                        hipMemcpyHostToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.tt, tt.data(), tt.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   if (!rf.empty())
     EC_HIP(hipMemcpyAsync(h->b.rf, rf.data(), rf.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
-  EC_HIP(hipMemsetAsync(h->b.iface, 0, (size_t)NC * 2 * MP * 2 * sizeof(T), h->s));
   EC_HIP(hipMemcpyAsync(h->b.tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
-  EC_HIP(hipMemsetAsync(ws + L.off_spec, 0, (size_t)ny * MP * 2 * sizeof(T), h->s));
-  EC_HIP(hipMemsetAsync(ws + L.off_phi, 0, (size_t)ny * L.P * sizeof(T), h->s));
-  EC_HIP(hipMemsetAsync(ws + L.off_mom, 0, 4 * (size_t)ny * nx * 8, h->s));
+  if (fresh) {
+    EC_HIP(hipMemsetAsync(h->b.iface, 0, (size_t)NC * 2 * MP * 2 * sizeof(T), h->s));
+    EC_HIP(hipMemsetAsync(ws + L.off_spec, 0, (size_t)ny * MP * 2 * sizeof(T), h->s));
+    EC_HIP(hipMemsetAsync(ws + L.off_phi, 0, (size_t)ny * L.P * sizeof(T), h->s));
+    EC_HIP(hipMemsetAsync(ws + L.off_mom, 0, 4 * (size_t)ny * nx * 8, h->s));
+  }
   EC_HIP(hipStreamSynchronize(h->s));  // the host vectors go out of scope
   return LBM_EC_OK;
 }
@@ -532,6 +565,41 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
     if (e != hipSuccess) rc = fail(LBM_EC_EHIP, std::string("initial state: ") + hipGetErrorString(e));
   }
   return rc;
+}
+
+// Continuation at another electric Rayleigh number (the state is that of
+// lbm_ec_set_T): the charge populations are rescaled and re-referenced, the
+// constants and tables of the new T written, and the density rows of the
+// next step formed from the rescaled populations.  Waits for the stream.
+template <typename T>
+int continue_at_T(lbm_ec* h, double T_new) {
+  lbm_ec_params p = h->p;
+  p.T = T_new;
+  int rc = validate(&p);
+  if (rc) return rc;
+  unsigned char* ws = (unsigned char*)h->b.f[0] - h->L.off_f[0];
+  const double eps_new = lattice_eps(p);
+  const double scale = eps_new / h->c.eps;
+  const RefRows ref = reference_rows(p, eps_new, sizeof(T) == 8 ? 40 : 18);
+  std::vector<double> r_new(p.ny);
+  for (int j = 0; j < p.ny; ++j) r_new[j] = 36.0 * ref.q[j];
+  EC_HIP(hipMemcpyAsync(h->b.rowsd + (size_t)ec::ROWD_RNEXT * p.ny, r_new.data(), sizeof(double) * p.ny,
+                        hipMemcpyHostToDevice, h->s));
+  // the reference rows use the force slope rounded for the storage type;
+  // the state is defined by the slope the FP64 rows use (s_init)
+  const double ddelta = (ref.s_ref - ref.s_init) - (h->c.s_ref - h->c.s_init);
+  EC_HIP(ec::launch_continue<T>(h->c, h->b, h->cur, scale, ddelta, h->s));
+  EC_HIP(hipStreamSynchronize(h->s));  // r_new goes out of scope
+  h->p = p;
+  if ((rc = setup<T>(h, ws, false))) return rc;
+  EC_HIP(ec::launch_density<T>(h->c, h->b, h->cur, h->tu, h->s));
+  hipError_t e = hipStreamSynchronize(h->s);
+  if (e != hipSuccess) return fail(LBM_EC_EHIP, std::string("continuation: ") + hipGetErrorString(e));
+  return LBM_EC_OK;
+}
+
+int continue_at(lbm_ec* h, double T_new) {
+  return h->fp32 ? continue_at_T<float>(h, T_new) : continue_at_T<double>(h, T_new);
 }
 
 }  // namespace
@@ -882,6 +950,15 @@ int lbm_ec_batch_history(lbm_ec_batch_t* B, int32_t slot, double* out, int32_t r
   return LBM_EC_OK;
 }
 
+int lbm_ec_batch_set_T(lbm_ec_batch_t* B, int32_t slot, double T) {
+  if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
+  int rc = pull_state(B);
+  if (rc) return rc;
+  if ((rc = continue_at(&B->slots[slot].inst, T))) return rc;
+  B->dirty = true;  // the slot's constants changed
+  return LBM_EC_OK;
+}
+
 int lbm_ec_batch_release(lbm_ec_batch_t* B, int32_t slot) {
   if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
   int rc = pull_state(B);
@@ -1002,6 +1079,11 @@ int lbm_ec_step(lbm_ec_t* h, int64_t n) {
   if (h->p.precision == LBM_EC_FP64) return run_steps<double, double>(h, n);
   if (h->p.precision == LBM_EC_FP32_DEV) return run_steps<float, float>(h, n);
   return run_steps<float, double>(h, n);
+}
+
+int lbm_ec_set_T(lbm_ec_t* h, double T) {
+  if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
+  return continue_at(h, T);
 }
 
 int64_t lbm_ec_steps_done(const lbm_ec_t* h) { return h ? h->steps : -1; }

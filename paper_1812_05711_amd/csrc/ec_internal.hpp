@@ -41,8 +41,10 @@ constexpr int kStatsBands = 1024;
 
 // Doubles per row of a batch slot's diagnostics history: step, rms u_y,
 // max |u|, sum of rho_c, amplitude of the first x mode of u_y (lattice
-// units), number of unhealthy nodes (non-finite moments or rho <= 0).
-constexpr int kHistCols = 6;
+// units), number of unhealthy nodes (non-finite moments or rho <= 0), the
+// collector current (charge the next streaming takes out through the upper
+// electrode, lattice units).
+constexpr int kHistCols = 7;
 
 // Rows per chunk of the partitioned per-wavenumber solves.
 constexpr int kChunk = 32;
@@ -117,6 +119,7 @@ enum RowTableD {
   ROWD_EYM,          // x-mean field E_y(j) (written each step)
   ROWD_PHIM,         // x-mean potential (written each step)
   ROWD_DFY,          // r(j) E_y mean(j) - s/3: x-mean force less the reference force
+  ROWD_RNEXT,        // r(j) of a new T while the state is re-referenced to it
   ROWD_COUNT
 };
 
@@ -211,6 +214,18 @@ hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_
 // cur: the buffer holding the post-collision populations (boundary charge)
 template <typename T>
 hipError_t launch_stats(const Consts& c, const Bufs& b, int cur, hipStream_t s);
+
+// Continuation at another T: the post-collision charge populations g[cur]
+// and the charge moment become scale (their reference + themselves) less the
+// new reference, with the old reference row in ROWD_R and the new one in
+// ROWD_RNEXT; the fluid deviations f[cur] and the density moment follow the
+// change ddelta of the storage rounding of the reference force slope.
+template <typename T>
+hipError_t launch_continue(const Consts& c, const Bufs& b, int cur, double scale, double ddelta, hipStream_t s);
+// The charge density rows the next step reads (what the collide tiles form
+// from the populations they write), formed from the stored g[cur].
+template <typename T>
+hipError_t launch_density(const Consts& c, const Bufs& b, int cur, const Tuning& tu, hipStream_t s);
 
 // LDS bytes of a collide tile (ten rows of nx values of T).
 template <typename T>

@@ -1243,7 +1243,9 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
 //
 // LDS: ten arrays of nx values of T: the six x movers of the current row,
 // own g*_4, the incomplete P of the current and of the previous row, U.
-template <typename T, typename C, bool PULL, bool EMIT>
+// DENS: no collision; g* is read from Gin as stored (the density of a state
+// whose post-collision populations were changed in place).
+template <typename T, typename C, bool PULL, bool EMIT, bool DENS = false>
 __device__ __forceinline__ void collide_tile(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
                                              T* __restrict__ Fout, T* __restrict__ Gout, const T* __restrict__ phi,
                                              const T* __restrict__ rows, const double* __restrict__ rowsd,
@@ -1270,7 +1272,10 @@ __device__ __forceinline__ void collide_tile(const Consts& c, const T* __restric
     T* Pprev = ((r - j0) & 1) ? Pa : Pb;  // P(r-1), complete
     for (int x = threadIdx.x; x < nx; x += blockDim.x) {
       T gt[9];
-      collide_node<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, x, r, gt);
+      if constexpr (DENS)
+        local_pop<T>(c, Gin, x, r, gt);
+      else
+        collide_node<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, x, r, gt);
       m1[x] = gt[1];
       m5[x] = gt[5];
       m8[x] = gt[8];
@@ -1310,6 +1315,51 @@ __global__ void __launch_bounds__(1024) k_collide(Consts c, const T* __restrict_
                                                   const double* __restrict__ rowsd, double* __restrict__ mom,
                                                   T* __restrict__ rq, T* __restrict__ eu, T* __restrict__ ed) {
   collide_tile<T, C, PULL, EMIT>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, mom, rq, eu, ed, blockIdx.x);
+}
+
+// The tiles' charge density sums from the stored post-collision g*.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_density(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
+                                                  T* __restrict__ rq, T* __restrict__ eu, T* __restrict__ ed) {
+  collide_tile<T, T, false, false, true>(c, nullptr, G, nullptr, nullptr, nullptr, rows, nullptr, nullptr, rq, eu,
+                                         ed, blockIdx.x);
+}
+
+// Continuation at another T (one thread per node), in FP64:
+//  * the full post-collision charge populations R_i + g_i are scaled by
+//    `scale` (the ratio of the new charge unit eps / H^2 to the old one) and
+//    re-referenced to the new rows, g_i <- scale g_i + w_i (scale r_old -
+//    r_new); the charge moment (rho_c - r of the last step) likewise;
+//  * the fluid populations keep their departure from the hydrostatic state
+//    w_i (rho_ref + c_iy s / 2), s its force slope.  The stored deviations
+//    already are that departure when the reference rows use s itself; where
+//    they use s rounded for the storage type (s_T = s + delta), they move by
+//    -w_i (delta_new - delta_old) (y_c + c_iy / 2), y_c = j + 1/2 - H/2, and
+//    the density moment by -(delta_new - delta_old) y_c.  ddelta = delta_new -
+//    delta_old (zero in FP64 storage, where nothing is rewritten).
+template <typename T>
+__global__ void __launch_bounds__(256) k_continue(Consts c, T* __restrict__ F, T* __restrict__ G,
+                                                  double* __restrict__ mom, const double* __restrict__ rowsd,
+                                                  double scale, double ddelta) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= c.nx) return;
+  const double d = scale * rowsd[ROWD_R * c.ny + j] - rowsd[ROWD_RNEXT * c.ny + j];
+  const double wv[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                        1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  const double cyv[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const size_t plane = (size_t)c.ny * c.P, idx = (size_t)j * c.P + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) G[i * plane + idx] = (T)(scale * (double)G[i * plane + idx] + wv[i] * d);
+  const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
+  mom[3 * n + k] = scale * mom[3 * n + k] + d;
+  if (ddelta != 0.0) {
+    const double yc = ((double)j + 0.5) - 0.5 * c.H;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      F[i * plane + idx] = (T)((double)F[i * plane + idx] - wv[i] * ddelta * (yc + 0.5 * cyv[i]));
+    mom[k] -= ddelta * yc;
+  }
 }
 
 // ------------------------------------------------------------ init kernels
@@ -1619,10 +1669,10 @@ __global__ void __launch_bounds__(1024) kb_collide(const SlotDesc* __restrict__ 
                                     (T*)d.b.rq, (T*)d.b.eu, (T*)d.b.ed, b);
 }
 // End of a batched step, one block per slot: the diagnostics of a slot that
-// emitted moments this step (rms u_y, max |u| and the total charge, into its
-// history), then the device-side advance of every active slot (flip the
+// emitted moments this step (into its history), then the device-side advance of every active slot (flip the
 // buffers, count the step, retire the slot at its target), so a captured
 // multi-step graph needs no host updates.
+template <typename T>
 __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D, const int* __restrict__ off,
                                                         int ns) {
   __shared__ double red[16];
@@ -1663,6 +1713,18 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
         ci = wave_sum(ci);
         a1 = fmax(a1, sqrt(cr * cr + ci * ci) / (double)nx);
       }
+      // collector current: what leaves through the upper electrode in the
+      // next streaming, from the post-collision populations just written
+      // (the reference rows cancel between the up and the down directions)
+      const T* G = (const T*)d.b.g[1 - d.cur];
+      const size_t plane = (size_t)ny * d.c.P, top = (size_t)(ny - 1) * d.c.P;
+      double cur_out = 0;
+      for (int x = threadIdx.x; x < nx; x += blockDim.x)
+        cur_out += ((double)G[2 * plane + top + x] + (double)G[5 * plane + top + x] +
+                    (double)G[6 * plane + top + x]) -
+                   ((double)G[4 * plane + top + x] + (double)G[7 * plane + top + x] +
+                    (double)G[8 * plane + top + x]);
+      cur_out = block_sum(cur_out, red);
       suy = block_sum(suy, red);
       srho_c = block_sum(srho_c, red);
       mu = block_max(mu, red);
@@ -1676,6 +1738,7 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
         h[3] = srho_c;
         h[4] = a1;
         h[5] = bad;
+        h[6] = cur_out;
       }
     }
   }
@@ -1733,7 +1796,7 @@ hipError_t launch_batch_step(const SlotDesc* d_desc, const int* d_off, const int
     hipLaunchKernelGGL((kb_collide<T, C>), dim3(totals[BK_COLLIDE]), dim3(tu.cbx * tu.cby), collide_lds, s, d_desc,
                        d_off + BK_COLLIDE * row, ns);
   if (totals[BK_STATS])
-    hipLaunchKernelGGL(kb_stats_advance, dim3(totals[BK_STATS]), dim3(256), 0, s, D, d_off + BK_STATS * row, ns);
+    hipLaunchKernelGGL(kb_stats_advance<T>, dim3(totals[BK_STATS]), dim3(256), 0, s, D, d_off + BK_STATS * row, ns);
   return hipGetLastError();
 }
 
@@ -1865,6 +1928,20 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, int cur, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_continue(const Consts& c, const Bufs& b, int cur, double scale, double ddelta, hipStream_t s) {
+  dim3 blk(256), grd((c.nx + 255) / 256, c.ny);
+  hipLaunchKernelGGL(k_continue<T>, grd, blk, 0, s, c, (T*)b.f[cur], (T*)b.g[cur], b.mom, b.rowsd, scale, ddelta);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_density(const Consts& c, const Bufs& b, int cur, const Tuning& tu, hipStream_t s) {
+  hipLaunchKernelGGL(k_density<T>, dim3(collide_tiles(c)), dim3(tu.cbx * tu.cby), collide_lds_bytes<T>(c.nx), s, c,
+                     (const T*)b.g[cur], (const T*)b.rows, (T*)b.rq, (T*)b.eu, (T*)b.ed);
+  return hipGetLastError();
+}
+
 #define EC_INSTANTIATE(T)                                                                                   \
   template hipError_t launch_init_charge<T>(const Consts&, const Bufs&, hipStream_t);                       \
   template hipError_t launch_init_populations<T>(const Consts&, const Bufs&, int, hipStream_t);             \
@@ -1875,7 +1952,9 @@ hipError_t launch_stats(const Consts& c, const Bufs& b, int cur, hipStream_t s) 
   template hipError_t launch_fields<T>(const Consts&, const Bufs&, double*, double*, double*, double*,       \
                                        double*, hipStream_t);                                               \
   template hipError_t launch_charge_in<T>(const Consts&, const Bufs&, const double*, hipStream_t);          \
-  template hipError_t launch_stats<T>(const Consts&, const Bufs&, int, hipStream_t);
+  template hipError_t launch_stats<T>(const Consts&, const Bufs&, int, hipStream_t);                        \
+  template hipError_t launch_continue<T>(const Consts&, const Bufs&, int, double, double, hipStream_t);     \
+  template hipError_t launch_density<T>(const Consts&, const Bufs&, int, const Tuning&, hipStream_t);
 
 EC_INSTANTIATE(double)
 EC_INSTANTIATE(float)

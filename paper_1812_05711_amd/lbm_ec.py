@@ -18,8 +18,10 @@ FP64, FP32_DEV, FP32_DEV_F64MATH = 0, 1, 2
 INIT_NOISE, INIT_EQ29, INIT_REST = 0, 1, 2
 RATES_ANTISYMMETRIC, RATES_SYMMETRIC = 0, 1
 # columns of a batch history row: step, rms u_y, max |u|, sum of rho_c,
-# amplitude of the first x mode of u_y (lattice units), unhealthy nodes
-HIST_COLS = 6
+# amplitude of the first x mode of u_y (lattice units), unhealthy nodes,
+# collector current (lattice units)
+HIST_COLS = 7
+HIST_CURRENT = 6
 
 _PRECISION = {"fp64": FP64, "fp32": FP32_DEV, "fp32_dev": FP32_DEV, "fp32_f64math": FP32_DEV_F64MATH}
 _INIT = {"noise": INIT_NOISE, "eq29": INIT_EQ29, "rest": INIT_REST}
@@ -127,6 +129,10 @@ def lib():
     L.lbm_ec_debug_poison.restype = ctypes.c_int
     L.lbm_ec_batch_debug_poison.argtypes = [vp, i32]
     L.lbm_ec_batch_debug_poison.restype = ctypes.c_int
+    L.lbm_ec_set_T.argtypes = [vp, ctypes.c_double]
+    L.lbm_ec_set_T.restype = ctypes.c_int
+    L.lbm_ec_batch_set_T.argtypes = [vp, i32, ctypes.c_double]
+    L.lbm_ec_batch_set_T.restype = ctypes.c_int
     L.lbm_ec_destroy.argtypes = [vp]
     L.lbm_ec_destroy.restype = None
     L.lbm_ec_last_error.argtypes = []
@@ -222,6 +228,11 @@ class Simulation:
 
     def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+
+    def set_T(self, T):
+        """Continue the run at electric Rayleigh number T (lbm_ec_set_T)."""
+        _check(lib().lbm_ec_set_T(self._h, float(T)))
+        self.params.T = float(T)
 
     def debug_poison(self):
         """Test hook: a NaN into one population of the current state."""
@@ -345,6 +356,10 @@ class Batch:
 
     def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_batch_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+
+    def set_T(self, slot, T):
+        """Continue the slot at electric Rayleigh number T (lbm_ec_batch_set_T)."""
+        _check(lib().lbm_ec_batch_set_T(self._h, int(slot), float(T)))
 
     def debug_poison(self, slot):
         """Test hook: a NaN into one population of the slot's current state."""
