@@ -31,6 +31,12 @@ Prints one JSON line:
                  autotuned launch shapes, one batch (captured HIP graphs),
                  against the same instances run one at a time through
                  lbm_ec_step (timed over 1000 steps each, scaled to 20000)
+  hysteresis     Ne_0 = I / I_0 on both branches of section V.2 in one batch
+                 on a 61 x 50 channel (C = 10, M = 10, Fe = 4000, FP32
+                 storage): runs from rest at T = 155, 160, 165; one run whose
+                 vortices form at T = 200 (12 ionic times), then continued at
+                 T = 150, 120, 110, 108, 106, 104 (6 ionic times each);
+                 brackets of T_c and T_f (paper: 163.4 and 108.7), run time
 """
 
 import argparse
@@ -157,6 +163,23 @@ def serve_section(n, warmup, budget_gb):
     return summary
 
 
+def hysteresis_section():
+    from paper_1812_05711_amd import hysteresis
+
+    rise, fall = (155.0, 160.0, 165.0), (200.0, 150.0, 120.0, 110.0, 108.0, 106.0, 104.0)
+    log(f"hysteresis: 61 x 50, rising {rise}, falling {fall}")
+    r = hysteresis.run(nx=61, ny=50, T_rise=rise, T_fall=fall, start_t0=12.0, dwell_t0=6.0,
+                       progress=lambda m: log("hysteresis: " + m))
+    log(f"hysteresis: T_c in {r['T_c_bracket']}, T_f in {r['T_f_bracket']}, {r['seconds']:.1f} s")
+    keep = ("grid", "steps", "slots", "seconds", "us_per_step", "mlups", "healthy", "rising", "falling",
+            "T_c_bracket", "T_f_bracket", "start_t0", "dwell_t0")
+    out = {k: r[k] for k in keep}
+    out["rising"] = [[T, round(v, 5)] for T, v in r["rising"]]
+    out["falling"] = [[T, round(v, 5)] for T, v in r["falling"]]
+    out["paper"] = {"T_c": 163.4, "T_f": 108.7}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +192,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-hysteresis", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -260,6 +284,7 @@ def main():
     out["sweep"] = None if args.no_sweep else sweep_section(args.sweep_steps, args.sweep_plain_steps)
     out["serve"] = None if args.no_serve else serve_section(args.serve_requests, args.serve_warmup,
                                                             args.serve_budget_gb)
+    out["hysteresis"] = None if args.no_hysteresis else hysteresis_section()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nx, ny)
     else:
