@@ -59,3 +59,55 @@ def profiles(C: float, y: np.ndarray):
     rho_c = C * e0 / E
     phi = 1.0 - (e2**1.5 - e0**3) / (3.0 * C * e0)
     return E, rho_c, phi
+
+
+def steady_state_with_diffusion(C: float, Fe: float):
+    """The 1-D steady state of the model equations with charge diffusion
+    (section V.1 without the drift-only simplification of Eq. 27-28), the
+    continuum solution the lattice hydrostatic state converges to.
+
+    Nondimensional (gap 1, potential drop 1, eps = 1, current in units of the
+    mobility): phi' = -E, E' = rho_c (Gauss), and the uniform current
+    J = rho_c E - rho_c' / Fe, i.e. rho_c' = Fe (rho_c E - J); with
+    phi(0) = 1, phi(1) = 0, rho_c(0) = C at the injector and rho_c'(1) = 0 at
+    the collector (the zero normal gradient of Table I as read).
+
+    Solved by shooting from the collector, where the unknowns are E(1) and J
+    (then rho_c(1) = J / E(1)): integrating towards the injector the stiff
+    charge mode decays, so an implicit Runge-Kutta (Radau IIA) integration at
+    rtol 1e-12 is stable; Newton iteration on phi(0) = 1, rho_c(0) = C.
+    Returns (J, f) with f(y) -> (E(y), rho_c(y), phi(y)) for y in [0, 1].
+    """
+    from scipy.integrate import solve_ivp
+    from scipy.optimize import fsolve
+
+    def rhs(y, Y, J):
+        _, E, r = Y
+        return [-E, r, Fe * (r * E - J)]
+
+    def integrate(q, dense=False):
+        E1, J = q
+        return solve_ivp(rhs, (1.0, 0.0), [0.0, E1, J / E1], args=(J,), method="Radau", rtol=1e-12,
+                         atol=1e-14, dense_output=dense)
+
+    def miss(q):
+        s = integrate(q)
+        return [s.y[0, -1] - 1.0, s.y[2, -1] - C]
+
+    import warnings
+
+    e0 = field_at_injector(C)
+    with warnings.catch_warnings():
+        # the step tolerance is below what the residual allows; the residual
+        # is checked below
+        warnings.simplefilter("ignore", RuntimeWarning)
+        q = fsolve(miss, [math.sqrt(e0 * e0 + 2.0 * C * e0), C * e0], xtol=1e-14)
+    if max(abs(v) for v in miss(q)) > 1e-10:
+        raise RuntimeError("shooting did not converge")
+    sol = integrate(q, dense=True).sol
+
+    def f(y):
+        Y = sol(np.asarray(y, dtype=np.float64))
+        return Y[1], Y[2], Y[0]
+
+    return float(q[1]), f
