@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-hysteresis", action="store_true")
+    ap.add_argument("--y-solver", default="tridiagonal", choices=["tridiagonal", "spectral"],
+                    help="y solve of the m >= 1 modes (spectral: the odd-extension route of Eq. 21-25)")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -212,6 +214,7 @@ def main():
     nx, ny = args.nx, args.ny
     log(f"create {nx}x{ny} {args.precision}")
     sim = Simulation(device="cuda:0", nx=nx, ny=ny, precision=args.precision, **WORKLOAD)
+    sim.set_y_solver(args.y_solver)
     torch.cuda.synchronize()
     tuning = None
     if not args.no_tune:
@@ -269,7 +272,7 @@ def main():
         "config": {"workload": f"coupled TRT-LBM / FFT-Poisson electroconvection step, {nx}x{ny}, "
                                f"{'FP64' if args.precision == 'fp64' else 'FP32-deviation'} storage, "
                                "T=500 C=10 M=10 Fe=4000, seeded charge noise 1e-4",
-                   "nx": nx, "ny": ny, "precision": args.precision},
+                   "nx": nx, "ny": ny, "precision": args.precision, "y_solver": args.y_solver},
         "roofline": {"bound": "hbm", "kernel": "collide-stream", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": c_bytes, "avg_launch_us": c_avg_s * 1e6},

@@ -73,6 +73,12 @@ enum {
   LBM_EC_INIT_REST = 2   /* rho = 1, u = 0, no charge (flow tests) */
 };
 
+/* y solve of the x wavenumbers m >= 1 (lbm_ec_set_y_solver) */
+enum {
+  LBM_EC_Y_TRIDIAGONAL = 0, /* chunked tridiagonal systems (default) */
+  LBM_EC_Y_SPECTRAL = 1     /* odd extension and transform in y (Eq. 21-25) */
+};
+
 /* which TRT rate of the charge lattice carries the diffusivity D_c */
 enum {
   LBM_EC_RATES_ANTISYMMETRIC = 0, /* D_c = cs2 (1/w_g- - 1/2); Lambda_g sets
@@ -203,6 +209,21 @@ int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes);
  * instance is then unchanged).  A checkpoint records T: lbm_ec_load refuses
  * one taken at another T. */
 int lbm_ec_set_T(lbm_ec_t* h, double T);
+
+/* Chooses how the Poisson solve of an instance treats the y direction of the
+ * x wavenumbers m >= 1 (the x-mean mode is always solved in FP64 flux form):
+ * LBM_EC_Y_TRIDIAGONAL (default) solves one tridiagonal system per m in
+ * 32-row chunks with an interface system; LBM_EC_Y_SPECTRAL takes the
+ * paper's route of Eq. 21-25: each column of the spectrum is extended oddly
+ * about the half-cell electrode positions to length 2 ny, transformed in y,
+ * divided by the symbol -(kappa_m^2 + 4 sin^2(pi k / (2 ny))) and
+ * transformed back.  Both invert the same discrete operator, so they agree
+ * to rounding.  The spectral route holds two columns of 2 ny complex values
+ * in LDS: EINVAL when that exceeds 160 KiB (ny > 2560 in FP64 storage,
+ * ny > 5120 in FP32).  Applies to lbm_ec_step and lbm_ec_poisson from the
+ * next call on; batches always use the tridiagonal solve.  Waits for the
+ * stream. */
+int lbm_ec_set_y_solver(lbm_ec_t* h, int32_t solver);
 
 /* Kernel timing for measurement.  lbm_ec_profile_begin starts recording a
  * HIP event pair around every kernel of the classes whose bit is set in

@@ -96,7 +96,7 @@ struct Layout {
   int P, M, MP, NC, KP;
   size_t tsize;
   size_t off_f[2], off_g[2], off_phi, off_rq, off_eu, off_ed, off_spec, off_tt, off_ends, off_gh, off_rf, off_iface,
-      off_tw, off_rows,
+      off_tw, off_twy, off_rows,
       off_rowsd, off_dmean, off_mom, off_stats, off_spart, total;
 };
 
@@ -137,6 +137,7 @@ Layout make_layout(const lbm_ec_params& p) {
   L.off_rf = take((size_t)L.MP * ec::RF_COUNT * L.KP * L.tsize);
   L.off_iface = take(nc * 2 * L.MP * 2 * L.tsize);
   L.off_tw = take(nx * 4 * L.tsize);
+  L.off_twy = take(ny * 8 * L.tsize);
   L.off_rows = take(ec::ROW_COUNT * ny * L.tsize);
   L.off_rowsd = take(ec::ROWD_COUNT * ny * 8);
   L.off_dmean = take((ny + 1) * 8);
@@ -190,6 +191,8 @@ struct lbm_ec {
   ec::Consts c;
   ec::Bufs b;
   ec::FftPlan plan;
+  ec::FftPlan plan_y;  // length 2 ny (spectral y solve)
+  int ysolver;         // LBM_EC_Y_TRIDIAGONAL or LBM_EC_Y_SPECTRAL
   hipStream_t s;
   int cur;  // buffer holding the latest post-collision populations
   int64_t steps;
@@ -242,6 +245,36 @@ double lattice_eps(const lbm_ec_params& p) {
   const double nu = kCs2 * (p.tau_plus - 0.5);
   const double K = nu * p.T / (p.M * p.M);
   return (p.M * K) * (p.M * K);
+}
+
+// Twiddles of a transform plan: [n] complex exp(-2 pi i k / n), then for
+// each pass of a register radix (2, 3, 4, 5, 8) and each k < Ns its R - 1
+// factors exp(-2 pi i r k / (Ns R)) side by side (at most n more).
+template <typename T>
+std::vector<T> twiddle_table(const ec::FftPlan& pl) {
+  const int n = pl.n;
+  std::vector<T> tw(4 * (size_t)n, T(0));
+  const long double twopi = 2.0L * 3.14159265358979323846264338327950288L;
+  for (int k = 0; k < n; ++k) {
+    const long double a = twopi * (long double)k / (long double)n;
+    tw[2 * k] = (T)cosl(a);
+    tw[2 * k + 1] = (T)(-sinl(a));
+  }
+  size_t o = 2 * (size_t)n;
+  long long Ns = 1;
+  for (int p = 0; p < pl.nr; ++p) {
+    const int R = pl.r[p];
+    if (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
+      for (long long k = 0; k < Ns; ++k)
+        for (int r = 1; r < R; ++r) {
+          const long double a = twopi * (long double)(r * k) / (long double)(Ns * R);
+          tw[o++] = (T)cosl(a);
+          tw[o++] = (T)(-sinl(a));
+        }
+    }
+    Ns *= R;
+  }
+  return tw;
 }
 
 // Lattice constants (Eq. 16-17, Eq. 26 with rho = 1, dphi0 = 1, H = ny) and
@@ -413,29 +446,7 @@ int setup(lbm_ec* h, unsigned char* ws, bool fresh = true) {
   // pass of radix R in {2, 3, 4, 5, 8} (Ns the product of the earlier
   // radices) and each k < Ns the R - 1 factors exp(-2 pi i r k / (Ns R)),
   // r = 1 .. R-1, next to each other (a butterfly reads them contiguously)
-  std::vector<T> tw(4 * (size_t)nx, T(0));
-  const long double twopi = 2.0L * 3.14159265358979323846264338327950288L;
-  for (int k = 0; k < nx; ++k) {
-    const long double a = twopi * (long double)k / (long double)nx;
-    tw[2 * k] = (T)cosl(a);
-    tw[2 * k + 1] = (T)(-sinl(a));
-  }
-  {
-    size_t o = 2 * (size_t)nx;
-    long long Ns = 1;
-    for (int p = 0; p < h->plan.nr; ++p) {
-      const int R = h->plan.r[p];
-      if (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
-        for (long long k = 0; k < Ns; ++k)
-          for (int r = 1; r < R; ++r) {
-            const long double a = twopi * (long double)(r * k) / (long double)(Ns * R);
-            tw[o++] = (T)cosl(a);
-            tw[o++] = (T)(-sinl(a));
-          }
-      }
-      Ns *= R;
-    }
-  }
+  const std::vector<T> tw = twiddle_table<T>(h->plan);
   EC_HIP(hipMemcpyAsync(h->b.rows, rows.data(), rows.size() * sizeof(T), hipMemcpyHostToDevice, h->s));
   // rows 0 .. ROWD_RC_CLOSED are fixed by the parameters, the others are
   // written by the steps
@@ -486,7 +497,10 @@ int prof_mark(lbm_ec* h, int cls, bool end) {
 template <typename T>
 int poisson_chain(lbm_ec* h, int mode, int src) {
   EC_TIMED(h, KC_FORWARD, (ec::launch_forward<T>(h->c, h->b, h->plan, mode, src, h->tu, h->s)));
-  EC_TIMED(h, KC_TRIDIAG, (ec::launch_tridiag<T>(h->c, h->b, h->s)));
+  if (h->ysolver == LBM_EC_Y_SPECTRAL)
+    EC_TIMED(h, KC_TRIDIAG, (ec::launch_yspec<T>(h->c, h->b, h->plan_y, h->s)));
+  else
+    EC_TIMED(h, KC_TRIDIAG, (ec::launch_tridiag<T>(h->c, h->b, h->s)));
   EC_TIMED(h, KC_INVERSE, (ec::launch_inverse<T>(h->c, h->b, h->plan, h->tu, h->s)));
   return LBM_EC_OK;
 }
@@ -529,6 +543,8 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
   h->s = s;
   h->fp32 = p->precision != LBM_EC_FP64;
   h->plan = make_plan(p->nx);
+  h->plan_y = make_plan(2 * p->ny);
+  h->ysolver = LBM_EC_Y_TRIDIAGONAL;
   h->tu = default_tuning(p->nx);
   h->b.f[0] = ws + L.off_f[0];
   h->b.f[1] = ws + L.off_f[1];
@@ -545,6 +561,7 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
   h->b.rf = ws + L.off_rf;
   h->b.iface = ws + L.off_iface;
   h->b.tw = ws + L.off_tw;
+  h->b.twy = ws + L.off_twy;
   h->b.rows = ws + L.off_rows;
   h->b.rowsd = (double*)(ws + L.off_rowsd);
   h->b.dmean = (double*)(ws + L.off_dmean);
@@ -1079,6 +1096,32 @@ int lbm_ec_step(lbm_ec_t* h, int64_t n) {
   if (h->p.precision == LBM_EC_FP64) return run_steps<double, double>(h, n);
   if (h->p.precision == LBM_EC_FP32_DEV) return run_steps<float, float>(h, n);
   return run_steps<float, double>(h, n);
+}
+
+int lbm_ec_set_y_solver(lbm_ec_t* h, int32_t solver) {
+  if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
+  if (solver != LBM_EC_Y_TRIDIAGONAL && solver != LBM_EC_Y_SPECTRAL) return fail(LBM_EC_EINVAL, "unknown y solver");
+  if (solver == LBM_EC_Y_SPECTRAL) {
+    const size_t lds = h->fp32 ? ec::yspec_lds_bytes<float>(h->p.ny) : ec::yspec_lds_bytes<double>(h->p.ny);
+    if (lds > ec::kMaxLds)
+      return fail(LBM_EC_EINVAL, "ny too large for the spectral y solve (two columns of 2 ny in LDS)");
+    const size_t n = 4 * (size_t)h->plan_y.n;
+    if (h->fp32) {
+      const std::vector<float> tw = twiddle_table<float>(h->plan_y);
+      EC_HIP(hipMemcpyAsync(h->b.twy, tw.data(), n * sizeof(float), hipMemcpyHostToDevice, h->s));
+      EC_HIP(hipStreamSynchronize(h->s));
+    } else {
+      const std::vector<double> tw = twiddle_table<double>(h->plan_y);
+      EC_HIP(hipMemcpyAsync(h->b.twy, tw.data(), n * sizeof(double), hipMemcpyHostToDevice, h->s));
+      EC_HIP(hipStreamSynchronize(h->s));
+    }
+    // the chunk corrections that the inverse transform adds vanish with
+    // zero interface values
+    EC_HIP(hipMemsetAsync(h->b.iface, 0, (size_t)h->L.NC * 2 * h->L.MP * 2 * h->L.tsize, h->s));
+    EC_HIP(hipStreamSynchronize(h->s));
+  }
+  h->ysolver = solver;
+  return LBM_EC_OK;
 }
 
 int lbm_ec_set_T(lbm_ec_t* h, double T) {

@@ -46,6 +46,9 @@ constexpr int kStatsBands = 1024;
 // electrode, lattice units).
 constexpr int kHistCols = 7;
 
+// LDS of one workgroup on gfx950.
+constexpr size_t kMaxLds = 160 * 1024;
+
 // Rows per chunk of the partitioned per-wavenumber solves.
 constexpr int kChunk = 32;
 // Chunk types: the whole column (one chunk), the first one (lower electrode
@@ -139,6 +142,7 @@ struct Bufs {
   void* iface;   // [P][2][MP] complex: interface values a_k (last row of chunk k),
                  //                      b_k (first row of chunk k+1)
   void* tw;      // [nx] complex twiddles exp(-2 pi i k / nx), then [<= nx] pass-major ones
+  void* twy;     // the same for the length 2 ny of the spectral y solve
   void* rows;    // ROW_COUNT x [ny]
   double* rowsd; // ROWD_COUNT x [ny]
   double* dmean; // [ny + 1] x-mean row differences D(-1) .. D(ny-1)
@@ -226,6 +230,14 @@ hipError_t launch_continue(const Consts& c, const Bufs& b, int cur, double scale
 // from the populations they write), formed from the stored g[cur].
 template <typename T>
 hipError_t launch_density(const Consts& c, const Bufs& b, int cur, const Tuning& tu, hipStream_t s);
+
+// Spectral y solve of the m >= 1 modes (Eq. 21-25), in place of the chunked
+// tridiagonal one: py is the plan of length 2 ny, b.twy its twiddles.
+template <typename T>
+hipError_t launch_yspec(const Consts& c, const Bufs& b, const FftPlan& py, hipStream_t s);
+// Its LDS bytes (two buffers of 2 ny complex values).
+template <typename T>
+size_t yspec_lds_bytes(int ny);
 
 // LDS bytes of a collide tile (ten rows of nx values of T).
 template <typename T>

@@ -1317,6 +1317,43 @@ __global__ void __launch_bounds__(1024) k_collide(Consts c, const T* __restrict_
   collide_tile<T, C, PULL, EMIT>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, mom, rq, eu, ed, blockIdx.x);
 }
 
+// Spectral y solve (Eq. 21-25), one block per x wavenumber m >= 1: the
+// column s_m(j) of the spectrum is extended oddly about the half-cell walls
+// to length N = 2 ny (entry N - 1 - j holds -s_m(j)), transformed, divided
+// by the symbol -(kappa_m^2 + 4 sin^2(pi k / N)) of the 3-point y difference
+// with the electrode ghosts and the spectral x derivative, transformed back
+// (1 / N), and the first ny entries overwrite the column: the same solution
+// as the tridiagonal systems, reached the paper's way.  The column is read
+// and written at the spectrum's row pitch (one element per row).
+template <typename T>
+__global__ void __launch_bounds__(256) k_yspec(Consts c, FftPlan py, const C2<T>* __restrict__ twy,
+                                               C2<T>* __restrict__ spec) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = py.n, ny = c.ny;
+  C2<T>* a = reinterpret_cast<C2<T>*>(smem);
+  C2<T>* b = a + N;
+  const int m = 1 + blockIdx.x;
+  const size_t MP = c.MP;
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+    const C2<T> v = spec[(size_t)j * MP + m];
+    a[j] = v;
+    a[N - 1 - j] = C2<T>{-v.re, -v.im};
+  }
+  __syncthreads();
+  C2<T>* r = fft_lds<T, false>(a, b, py, twy);
+  const int mf = min(m, c.nx - m);
+  const double kap = 2.0 * (double)mf / (double)c.nx;  // kappa_m / pi
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const double sn = sinpi((double)k / (double)N);
+    const double sym = -(M_PI * M_PI * kap * kap + 4.0 * sn * sn);
+    const T f = (T)(1.0 / (sym * (double)N));
+    r[k] = cscale(r[k], f);
+  }
+  __syncthreads();
+  C2<T>* o = fft_lds<T, true>(r, r == a ? b : a, py, twy);
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) spec[(size_t)j * MP + m] = o[j];
+}
+
 // The tiles' charge density sums from the stored post-collision g*.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_density(Consts c, const T* __restrict__ G, const T* __restrict__ rows,
@@ -1936,6 +1973,19 @@ hipError_t launch_continue(const Consts& c, const Bufs& b, int cur, double scale
 }
 
 template <typename T>
+size_t yspec_lds_bytes(int ny) {
+  return 2 * (size_t)(2 * ny) * sizeof(C2<T>);
+}
+
+template <typename T>
+hipError_t launch_yspec(const Consts& c, const Bufs& b, const FftPlan& py, hipStream_t s) {
+  if (c.M < 2) return hipSuccess;  // no m >= 1 modes
+  hipLaunchKernelGGL(k_yspec<T>, dim3(c.M - 1), dim3(256), yspec_lds_bytes<T>(c.ny), s, c, py,
+                     (const C2<T>*)b.twy, (C2<T>*)b.spec);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_density(const Consts& c, const Bufs& b, int cur, const Tuning& tu, hipStream_t s) {
   hipLaunchKernelGGL(k_density<T>, dim3(collide_tiles(c)), dim3(tu.cbx * tu.cby), collide_lds_bytes<T>(c.nx), s, c,
                      (const T*)b.g[cur], (const T*)b.rows, (T*)b.rq, (T*)b.eu, (T*)b.ed);
@@ -1954,7 +2004,9 @@ hipError_t launch_density(const Consts& c, const Bufs& b, int cur, const Tuning&
   template hipError_t launch_charge_in<T>(const Consts&, const Bufs&, const double*, hipStream_t);          \
   template hipError_t launch_stats<T>(const Consts&, const Bufs&, int, hipStream_t);                        \
   template hipError_t launch_continue<T>(const Consts&, const Bufs&, int, double, double, hipStream_t);     \
-  template hipError_t launch_density<T>(const Consts&, const Bufs&, int, const Tuning&, hipStream_t);
+  template hipError_t launch_density<T>(const Consts&, const Bufs&, int, const Tuning&, hipStream_t);         \
+  template hipError_t launch_yspec<T>(const Consts&, const Bufs&, const FftPlan&, hipStream_t);              \
+  template size_t yspec_lds_bytes<T>(int);
 
 EC_INSTANTIATE(double)
 EC_INSTANTIATE(float)

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_ec.so")
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, EBUSY = 0, 1, 2, 3, 4, 5
 FP64, FP32_DEV, FP32_DEV_F64MATH = 0, 1, 2
 INIT_NOISE, INIT_EQ29, INIT_REST = 0, 1, 2
+Y_TRIDIAGONAL, Y_SPECTRAL = 0, 1
 RATES_ANTISYMMETRIC, RATES_SYMMETRIC = 0, 1
 # columns of a batch history row: step, rms u_y, max |u|, sum of rho_c,
 # amplitude of the first x mode of u_y (lattice units), unhealthy nodes,
@@ -129,6 +130,8 @@ def lib():
     L.lbm_ec_debug_poison.restype = ctypes.c_int
     L.lbm_ec_batch_debug_poison.argtypes = [vp, i32]
     L.lbm_ec_batch_debug_poison.restype = ctypes.c_int
+    L.lbm_ec_set_y_solver.argtypes = [vp, i32]
+    L.lbm_ec_set_y_solver.restype = ctypes.c_int
     L.lbm_ec_set_T.argtypes = [vp, ctypes.c_double]
     L.lbm_ec_set_T.restype = ctypes.c_int
     L.lbm_ec_batch_set_T.argtypes = [vp, i32, ctypes.c_double]
@@ -228,6 +231,11 @@ class Simulation:
 
     def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
         _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+
+    def set_y_solver(self, solver):
+        """'tridiagonal' (default) or 'spectral' (lbm_ec_set_y_solver)."""
+        code = {"tridiagonal": Y_TRIDIAGONAL, "spectral": Y_SPECTRAL}.get(solver, solver)
+        _check(lib().lbm_ec_set_y_solver(self._h, int(code)))
 
     def set_T(self, T):
         """Continue the run at electric Rayleigh number T (lbm_ec_set_T)."""
