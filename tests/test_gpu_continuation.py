@@ -141,3 +141,26 @@ def test_batch_set_T_equals_alone_bitwise(precision):
     assert len(last) == 1
     assert last[0, HIST_CURRENT] == pytest.approx(-st["q_collector"], rel=1e-12)
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_f64math"])
+def test_fields_right_after_a_change(precision):
+    """lbm_ec_fields between lbm_ec_set_T and the next step: the charge keeps
+    its nondimensional value, the velocity its lattice value (u / u0 scales
+    by u0_old / u0_new = T_old / T_new), the density its departure from the
+    reference row."""
+    import torch
+
+    from paper_1812_05711_amd.lbm_ec import Simulation
+
+    sim = Simulation(device="cuda:0", precision=precision, **dict(BASE, nx=24, ny=20))
+    sim.step(15)
+    before = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    sim.set_T(150.0)
+    after = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    torch.cuda.synchronize()
+    sim.close()
+    np.testing.assert_allclose(after["rho_c"], before["rho_c"], rtol=1e-12, atol=0)
+    for k in ("ux", "uy"):
+        np.testing.assert_allclose(after[k], before[k] * (200.0 / 150.0), rtol=1e-12,
+                                   atol=1e-12 * np.abs(before[k]).max())
