@@ -172,7 +172,7 @@ def hysteresis_section():
                        progress=lambda m: log("hysteresis: " + m))
     log(f"hysteresis: T_c in {r['T_c_bracket']}, T_f in {r['T_f_bracket']}, {r['seconds']:.1f} s")
     keep = ("grid", "steps", "slots", "seconds", "us_per_step", "mlups", "healthy", "rising", "falling",
-            "T_c_bracket", "T_f_bracket", "start_t0", "dwell_t0")
+            "T_c_bracket", "T_f_bracket", "start_t0", "dwell_t0", "tuning")
     out = {k: r[k] for k in keep}
     out["rising"] = [[T, round(v, 5)] for T, v in r["rising"]]
     out["falling"] = [[T, round(v, 5)] for T, v in r["falling"]]
