@@ -1095,6 +1095,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Transf
   inverse_body<T, F>(c, spec, tt, iface, pl, tw, phi, blockIdx.x - 1);
 }
 
+// Workgroups are dealt to the eight XCDs in turn; block b takes index
+// start(b mod 8) + b / 8, start(x) = x q + min(x, r) for G = 8 q + r blocks (a
+// bijection onto 0 .. G-1), so that the blocks of one XCD take consecutive
+// indices and share their cache lines in that XCD's L2.
+__device__ __forceinline__ int xcd_order(int b, int G) {
+  const int q = G >> 3, r = G & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // ------------------------------------------- fused collide (and stream)
 // One thread per node.  PULL: gathers the pre-collision populations from the
 // post-collision arrays with the wall rules (the streaming of Eq. 8-9);
@@ -1332,7 +1341,7 @@ __global__ void __launch_bounds__(256) k_yspec(Consts c, FftPlan py, const C2<T>
   const int N = py.n, ny = c.ny;
   C2<T>* a = reinterpret_cast<C2<T>*>(smem);
   C2<T>* b = a + N;
-  const int m = 1 + blockIdx.x;
+  const int m = 1 + xcd_order(blockIdx.x, gridDim.x);  // neighbouring columns share cache lines
   const size_t MP = c.MP;
   for (int j = threadIdx.x; j < ny; j += blockDim.x) {
     const C2<T> v = spec[(size_t)j * MP + m];
@@ -1352,6 +1361,37 @@ __global__ void __launch_bounds__(256) k_yspec(Consts c, FftPlan py, const C2<T>
   __syncthreads();
   C2<T>* o = fft_lds<T, true>(r, r == a ? b : a, py, twy);
   for (int j = threadIdx.x; j < ny; j += blockDim.x) spec[(size_t)j * MP + m] = o[j];
+}
+
+// The same with the in-place transform, for columns whose length has only
+// register radices and at most kFftPerThread elements per thread of 512: one
+// column buffer in LDS, so that two blocks share a CU where the ping-pong
+// form fits one.
+template <typename T>
+__global__ void __launch_bounds__(512) k_yspec_ip(Consts c, FftPlan py, const C2<T>* __restrict__ twy,
+                                                  C2<T>* __restrict__ spec) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = py.n, ny = c.ny;
+  C2<T>* a = reinterpret_cast<C2<T>*>(smem);
+  const int m = 1 + xcd_order(blockIdx.x, gridDim.x);  // neighbouring columns share cache lines
+  const size_t MP = c.MP;
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+    const C2<T> v = spec[(size_t)j * MP + m];
+    a[j] = v;
+    a[N - 1 - j] = C2<T>{-v.re, -v.im};
+  }
+  __syncthreads();
+  fft_lds_ip<T, false, kFftPerThread>(a, py, twy);
+  const int mf = min(m, c.nx - m);
+  const double kap = 2.0 * (double)mf / (double)c.nx;  // kappa_m / pi
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const double sn = sinpi((double)k / (double)N);
+    const double sym = -(M_PI * M_PI * kap * kap + 4.0 * sn * sn);
+    a[k] = cscale(a[k], (T)(1.0 / (sym * (double)N)));
+  }
+  __syncthreads();
+  fft_lds_ip<T, true, kFftPerThread>(a, py, twy);
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) spec[(size_t)j * MP + m] = a[j];
 }
 
 // The tiles' charge density sums from the stored post-collision g*.
@@ -1980,8 +2020,12 @@ size_t yspec_lds_bytes(int ny) {
 template <typename T>
 hipError_t launch_yspec(const Consts& c, const Bufs& b, const FftPlan& py, hipStream_t s) {
   if (c.M < 2) return hipSuccess;  // no m >= 1 modes
-  hipLaunchKernelGGL(k_yspec<T>, dim3(c.M - 1), dim3(256), yspec_lds_bytes<T>(c.ny), s, c, py,
-                     (const C2<T>*)b.twy, (C2<T>*)b.spec);
+  if (fft_in_place(py, 512, kFftPerThread))
+    hipLaunchKernelGGL(k_yspec_ip<T>, dim3(c.M - 1), dim3(512), (size_t)py.n * sizeof(C2<T>), s, c, py,
+                       (const C2<T>*)b.twy, (C2<T>*)b.spec);
+  else
+    hipLaunchKernelGGL(k_yspec<T>, dim3(c.M - 1), dim3(256), yspec_lds_bytes<T>(c.ny), s, c, py,
+                       (const C2<T>*)b.twy, (C2<T>*)b.spec);
   return hipGetLastError();
 }
 
