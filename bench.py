@@ -204,7 +204,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the time step runs on a single GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(the time step runs on a single GPU: independent instances would shard across GPUs by "
+              "footprint, one large instance in y-slabs with one-row halo exchanges)", file=sys.stderr)
         sys.exit(2)
 
     import torch
