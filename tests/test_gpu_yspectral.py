@@ -103,3 +103,29 @@ def test_refused_solver_and_sizes():
         sim.set_y_solver(7)
     assert ei.value.code == EINVAL
     sim.close()
+
+
+def test_spectral_y_with_a_change_of_T():
+    """lbm_ec_set_T rewrites the tables of the new T and leaves the spectral
+    route's own (T-independent) twiddles in place."""
+    import torch
+
+    from oracle import Oracle
+    from paper_1812_05711_amd.lbm_ec import Simulation
+
+    kw = dict(BASE, nx=24, ny=20)
+    o = Oracle(Params(**kw))
+    o.step(15)
+    o.set_T(150.0)
+    o.step(20)
+    sim = Simulation(device="cuda:0", precision="fp64", **kw)
+    sim.set_y_solver("spectral")
+    sim.step(15)
+    sim.set_T(150.0)
+    sim.step(20)
+    g = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    torch.cuda.synchronize()
+    sim.close()
+    e = errors(g, o.fields())
+    for k in ("rho", "u", "rho_c", "phi"):
+        assert e[k] <= 1e-11, (k, e)
