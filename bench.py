@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-hysteresis", action="store_true")
+    ap.add_argument("--T", type=float, default=WORKLOAD["T"], help="electric Rayleigh number")
+    ap.add_argument("--noise-amp", type=float, default=WORKLOAD["noise_amp"], help="relative charge noise")
     ap.add_argument("--y-solver", default="tridiagonal", choices=["tridiagonal", "spectral"],
                     help="y solve of the m >= 1 modes (spectral: the odd-extension route of Eq. 21-25)")
     ap.add_argument("--serve-requests", type=int, default=600)
@@ -202,6 +204,7 @@ def main():
     ap.add_argument("--sweep-plain-steps", type=int, default=1000)
     args = ap.parse_args()
 
+    WORKLOAD.update(T=args.T, noise_amp=args.noise_amp)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the time step runs on a single GPU: independent instances would shard across GPUs by "
@@ -272,7 +275,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"coupled TRT-LBM / FFT-Poisson electroconvection step, {nx}x{ny}, "
                                f"{'FP64' if args.precision == 'fp64' else 'FP32-deviation'} storage, "
-                               "T=500 C=10 M=10 Fe=4000, seeded charge noise 1e-4",
+                               f"T={args.T:g} C=10 M=10 Fe=4000, seeded charge noise {args.noise_amp:g}",
                    "nx": nx, "ny": ny, "precision": args.precision, "y_solver": args.y_solver},
         "roofline": {"bound": "hbm", "kernel": "collide-stream", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
