@@ -113,6 +113,25 @@ def run_plain(configs, steps, device="cuda:0"):
     return total
 
 
+def threshold_configs(nx, ny, Ts, precision="fp64", C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25,
+                      Lambda_g=1e-6, seed=181205711):
+    """The threshold problem of section V.2 at one grid: the Eq. 29
+    perturbation on the hydrostatic rows, one instance per T."""
+    return [dict(nx=nx, ny=ny, T=float(T), C=C, M=M, Fe=Fe, tau_plus=tau_plus, Lambda=Lambda, Lambda_g=Lambda_g,
+                 init_mode="eq29", noise_amp=0.0, seed=seed, instance_id=i, precision=precision)
+            for i, T in enumerate(Ts)]
+
+
+def zero_crossing(Ts, rates):
+    """T where the growth rate changes sign, by linear interpolation between
+    the neighbouring T values that bracket it (None when none do)."""
+    pairs = sorted(zip(Ts, rates))
+    for (t0, r0), (t1, r1) in zip(pairs[:-1], pairs[1:]):
+        if r0 < 0.0 <= r1:
+            return t0 + (t1 - t0) * (-r0) / (r1 - r0)
+    return None
+
+
 def main(argv=None):
     """Command line: runs the seeded T sweep as one batch and prints the
     step time, the throughput and the growth rate of each instance."""
@@ -124,7 +143,21 @@ def main(argv=None):
     ap.add_argument("--emit-every", type=int, default=100)
     ap.add_argument("--precision", default="fp32_f64math", choices=["fp64", "fp32", "fp32_f64math"])
     ap.add_argument("--tuning", default=None, help="fft_threads,collide_bx,collide_by (default: autotuned)")
+    ap.add_argument("--threshold", default=None,
+                    help="NXxNY: instead of the seeded sweep, the Eq. 29 threshold problem at this grid for the "
+                         "T values of --T; prints the growth rates and their zero crossing")
+    ap.add_argument("--T", default="160,162,164,166", help="T values of --threshold (comma separated)")
     args = ap.parse_args(argv)
+    if args.threshold:
+        nx, ny = (int(v) for v in args.threshold.lower().split("x"))
+        Ts = [float(v) for v in args.T.split(",")]
+        cfgs = threshold_configs(nx, ny, Ts, precision=args.precision)
+        r = run_batched(cfgs, args.steps, emit_every=args.emit_every, tune=args.tuning is None)
+        for T, g in zip(Ts, r["growth"]):
+            print(f"T {T:8.3f}  growth rate {g:+.5f} per ionic time", flush=True)
+        print(f"zero crossing: T_c = {zero_crossing(Ts, r['growth'])}  ({args.steps} steps, "
+              f"{r['seconds']:.1f} s)", flush=True)
+        return
     cfgs = sweep_configs(n=args.instances, precision=args.precision)
     tuning = (tuple(int(v) for v in args.tuning.split(",")) if args.tuning
               else autotune.tune_batch(cfgs))

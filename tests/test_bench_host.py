@@ -8,6 +8,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -70,3 +71,13 @@ def test_growth_rate_fit():
     hist[:40, 1] = 1.0  # another column, not used by the default fit
     assert abs(growth_rate(hist, t0) - 0.7) < 1e-9
     assert abs(growth_rate(hist, t0, col=1)) < 1e-12
+
+
+def test_threshold_zero_crossing():
+    from paper_1812_05711_amd import sweep
+
+    assert sweep.zero_crossing([160.0, 162.0, 164.0], [-0.2, -0.1, 0.3]) == pytest.approx(162.5)
+    assert sweep.zero_crossing([164.0, 160.0], [0.3, -0.1]) == pytest.approx(161.0)
+    assert sweep.zero_crossing([160.0, 162.0], [-0.2, -0.1]) is None
+    cfgs = sweep.threshold_configs(122, 100, [160.0, 165.0])
+    assert [c["T"] for c in cfgs] == [160.0, 165.0] and all(c["init_mode"] == "eq29" for c in cfgs)
