@@ -116,7 +116,10 @@ int lbm_ec_params_default(lbm_ec_params* p);
 
 /* Checks a parameter set (see the field comments; also nx within the
  * widest grid of the chosen precision: 2048 in FP64, 4096 with FP32 storage,
- * since a collide tile holds ten rows of nx values in LDS).  Returns OK or
+ * since a collide tile holds ten rows of nx values in LDS; every real
+ * parameter finite; and the lattice mobility K = nu T / M^2, permittivity
+ * eps = (M K)^2, injected charge rho0 = C eps / ny^2 and diffusivity
+ * D_c = K / Fe finite, with K, eps and D_c positive).  Returns OK or
  * EINVAL. */
 int lbm_ec_validate(const lbm_ec_params* p);
 

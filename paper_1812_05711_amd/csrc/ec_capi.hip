@@ -158,7 +158,8 @@ int validate(const lbm_ec_params* p) {
                                    ") of this precision");
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_EC_EINVAL, "grid too large");
   if (!(p->tau_plus > 0.5) || !std::isfinite(p->tau_plus)) return fail(LBM_EC_EINVAL, "tau_plus must exceed 1/2");
-  if (!(p->Lambda > 0) || !(p->Lambda_g > 0)) return fail(LBM_EC_EINVAL, "Lambda and Lambda_g must be positive");
+  if (!(p->Lambda > 0) || !(p->Lambda_g > 0) || !std::isfinite(p->Lambda) || !std::isfinite(p->Lambda_g))
+    return fail(LBM_EC_EINVAL, "Lambda and Lambda_g must be positive and finite");
   if (!(p->T > 0) || !(p->M > 0) || !(p->Fe > 0) || !(p->C >= 0) || !std::isfinite(p->T) ||
       !std::isfinite(p->C) || !std::isfinite(p->M) || !std::isfinite(p->Fe))
     return fail(LBM_EC_EINVAL, "T, M, Fe must be positive and finite, C non-negative");
@@ -167,6 +168,16 @@ int validate(const lbm_ec_params* p) {
     return fail(LBM_EC_EINVAL, "unknown charge_rates");
   if (!std::isfinite(p->noise_amp) || !std::isfinite(p->body_force_x))
     return fail(LBM_EC_EINVAL, "noise_amp and body_force_x must be finite");
+  // the lattice constants of Eq. 16 and 26 (as setup forms them) must be
+  // finite and positive: extreme T, M or C overflow eps = (M K)^2 or rho0
+  const double nu = kCs2 * (p->tau_plus - 0.5);
+  const double K = nu * p->T / (p->M * p->M);
+  const double eps = (p->M * K) * (p->M * K);
+  const double rho0 = p->C * eps / ((double)p->ny * (double)p->ny);
+  const double Dc = K / p->Fe;
+  if (!(K > 0) || !(eps > 0) || !(Dc > 0) || !std::isfinite(K) || !std::isfinite(eps) || !std::isfinite(rho0) ||
+      !std::isfinite(Dc) || !std::isfinite(0.5 + Dc / kCs2))
+    return fail(LBM_EC_EINVAL, "the lattice constants (K, eps, rho0, D_c) of these parameters are not finite and positive");
   return LBM_EC_OK;
 }
 

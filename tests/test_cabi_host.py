@@ -66,3 +66,68 @@ def test_create_rejects_small_workspace_without_touching_the_device(E):
     code = E.lib().lbm_ec_create(ctypes.byref(p), ctypes.c_void_p(256), 16, None, ctypes.byref(h))
     assert code == E.ENOMEM
     assert "workspace" in E.lib().lbm_ec_last_error().decode()
+
+
+def _documented_verdict(d):
+    """lbm_ec_validate's rules as include/lbm_ec.h states them, restated."""
+    import math
+
+    fin = math.isfinite
+    if d["nx"] < 1 or d["ny"] < 3 or d["precision"] not in (0, 1, 2):
+        return False
+    if d["nx"] > (2048 if d["precision"] == 0 else 4096) or d["nx"] * d["ny"] > 2**31:
+        return False
+    if not (d["tau_plus"] > 0.5 and fin(d["tau_plus"])):
+        return False
+    if not (d["Lambda"] > 0 and d["Lambda_g"] > 0 and fin(d["Lambda"]) and fin(d["Lambda_g"])):
+        return False
+    if not (d["T"] > 0 and d["M"] > 0 and d["Fe"] > 0 and d["C"] >= 0 and
+            all(fin(d[k]) for k in ("T", "C", "M", "Fe"))):
+        return False
+    if d["init_mode"] not in (0, 1, 2) or d["charge_rates"] not in (0, 1):
+        return False
+    if not (fin(d["noise_amp"]) and fin(d["body_force_x"])):
+        return False
+    nu = (1.0 / 3.0) * (d["tau_plus"] - 0.5)
+    K = nu * d["T"] / (d["M"] * d["M"])
+    eps = (d["M"] * K) * (d["M"] * K)
+    rho0 = d["C"] * eps / (float(d["ny"]) * float(d["ny"]))
+    Dc = K / d["Fe"]
+    return (K > 0 and eps > 0 and Dc > 0 and fin(K) and fin(eps) and fin(rho0) and fin(Dc)
+            and fin(0.5 + Dc / (1.0 / 3.0)))
+
+
+def test_validation_follows_the_documented_rules(E):
+    """Random and extreme parameter sets: lbm_ec_validate accepts exactly
+    those the header's rules accept, and the workspace size is zero exactly
+    for the refused ones (and at least the four population arrays
+    otherwise)."""
+    hypothesis = pytest.importorskip("hypothesis")
+    st = hypothesis.strategies
+    special = st.sampled_from([0.0, -1.0, float("nan"), float("inf"), -float("inf"), 1e-300, 1e300])
+    real = lambda lo, hi: st.one_of(st.floats(lo, hi, allow_nan=False, allow_infinity=False), special)
+
+    @hypothesis.settings(max_examples=400, deadline=None, derandomize=True)
+    @hypothesis.given(
+        nx=st.one_of(st.integers(-2, 5000), st.sampled_from([1, 2048, 2049, 4096, 4097])),
+        ny=st.one_of(st.integers(-2, 600000), st.sampled_from([3, 2, 524288, 524289])),
+        T=real(1e-3, 1e4), C=real(0.0, 1e3), M=real(1e-2, 1e3), Fe=real(1e-2, 1e6),
+        tau_plus=real(0.3, 3.0), Lambda=real(1e-8, 10.0), Lambda_g=real(1e-8, 10.0),
+        precision=st.integers(-1, 3), init_mode=st.integers(-1, 3), charge_rates=st.integers(-1, 2),
+        noise_amp=real(-1.0, 1.0), body_force_x=real(-1e-3, 1e-3))
+    def check(**d):
+        p = E.Params()
+        E.lib().lbm_ec_params_default(ctypes.byref(p))
+        for k, v in d.items():
+            setattr(p, k, v)
+        ok = _documented_verdict(d)
+        code = E.lib().lbm_ec_validate(ctypes.byref(p))
+        assert code == (E.OK if ok else E.EINVAL), (d, code)
+        n = E.lib().lbm_ec_workspace_bytes(ctypes.byref(p))
+        if ok:
+            tsize = 8 if d["precision"] == 0 else 4
+            assert n >= 4 * 9 * d["nx"] * d["ny"] * tsize
+        else:
+            assert n == 0
+
+    check()
