@@ -38,3 +38,36 @@ def test_hydrostatic_state_converges_at_second_order():
     ey_o = cv.field_from_potential(fo["phi"][:, 0])
     assert rel_l2_error(prof[0.1][50][1], fo["rho_c"][:, 0]) < 1e-11
     assert rel_l2_error(prof[0.1][50][0], ey_o) < 1e-11
+
+
+def test_table2_at_100_rows():
+    """The GPU's 100-row hydrostatic states against Table II: for C = 0.1 the
+    L2 errors against the closed form are no larger than the paper's, and for
+    C = 10 a fit of the Eq. 27-28 form gives its rho_a and y_a to the printed
+    digits."""
+    import json
+    import os
+
+    from scipy.optimize import least_squares
+
+    from oracle import hydrostatic
+    from oracle.diagnostics import rel_l2_error
+    from paper_1812_05711_amd import convergence as cv
+
+    table = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table2_hydrostatic.json")))
+    prof, _ = cv.run(nys=(100,), Cs=(0.1, 10.0), n_t0=3.0, precision="fp64")
+    y = (np.arange(100) + 0.5) / 100
+    ey, rc = prof[0.1][100]
+    E, rho_c, _ = hydrostatic.profiles(0.1, y)
+    t = table["C=0.1"]
+    assert rel_l2_error(ey, E) < t["eL2_Ey"] and rel_l2_error(rc, rho_c) < t["eL2_rho_c"]
+    ey, rc = prof[10.0][100]
+
+    def res(q):
+        ra, ya = q
+        return np.concatenate([(ra / np.sqrt(y + ya) - rc) / np.linalg.norm(rc),
+                               (2 * ra * np.sqrt(y + ya) - ey) / np.linalg.norm(ey)])
+
+    ra, ya = least_squares(res, [0.5, 0.01], bounds=([0, 1e-7], [10, 100])).x
+    t = table["C=10"]
+    assert abs(ra - t["rho_a"]) <= 0.005 and abs(ya - t["y_a"]) <= 0.0005, (ra, ya)
