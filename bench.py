@@ -279,6 +279,7 @@ def main():
                    "nx": nx, "ny": ny, "precision": args.precision, "y_solver": args.y_solver},
         "roofline": {"bound": "hbm", "kernel": "collide-stream", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": (traffic / c_avg_s / 1e9) if traffic else None,
                      "algorithmic_bytes_per_launch": c_bytes, "avg_launch_us": c_avg_s * 1e6},
         "step_roofline": {"algorithmic_bytes_per_node": STEP_BYTES_PER_NODE[args.precision],
                           "roofline_mlups": roofline_mlups, "frac": mlups / roofline_mlups},
