@@ -79,14 +79,25 @@ def make_batch(configs, steps, emit_every=100, device="cuda:0", tuning=None):
     return b, slots
 
 
-def run_batched(configs, steps, emit_every=100, device="cuda:0", tune=True):
+def run_batched(configs, steps, emit_every=100, device="cuda:0", tune=True, progress=None, chunk=None):
     """Advances every instance `steps` steps as one batch.  Returns the wall
-    time of the stepping (creation excluded), the growth rates, the tuning."""
+    time of the stepping (creation excluded), the growth rates, the tuning.
+    With `progress`, the steps go in chunks of `chunk` and each chunk ends
+    with a call progress(message)."""
     tuning = autotune.tune_batch(configs, device=device) if tune else None
     b, slots = make_batch(configs, steps, emit_every, device, tuning)
     b.stream.synchronize()
     t = time.perf_counter()
-    b.step(steps)
+    if progress is None:
+        b.step(steps)
+    else:
+        done, chunk = 0, max(1, chunk or steps)
+        while done < steps:
+            n = min(chunk, steps - done)
+            b.step(n)
+            b.stream.synchronize()
+            done += n
+            progress(f"{done} of {steps} steps, {time.perf_counter() - t:.1f} s")
     b.stream.synchronize()
     dt = time.perf_counter() - t
     done = b.poll()
@@ -152,7 +163,10 @@ def main(argv=None):
         nx, ny = (int(v) for v in args.threshold.lower().split("x"))
         Ts = [float(v) for v in args.T.split(",")]
         cfgs = threshold_configs(nx, ny, Ts, precision=args.precision)
-        r = run_batched(cfgs, args.steps, emit_every=args.emit_every, tune=args.tuning is None)
+        import sys
+
+        r = run_batched(cfgs, args.steps, emit_every=args.emit_every, tune=args.tuning is None,
+                        progress=lambda m: print(m, file=sys.stderr, flush=True), chunk=200000)
         for T, g in zip(Ts, r["growth"]):
             print(f"T {T:8.3f}  growth rate {g:+.5f} per ionic time", flush=True)
         print(f"zero crossing: T_c = {zero_crossing(Ts, r['growth'])}  ({args.steps} steps, "
