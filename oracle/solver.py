@@ -56,8 +56,22 @@ def charge_noise(p: Params) -> np.ndarray:
     return xi.reshape(p.ny, p.nx)
 
 
+def eq29_profile(x, y, Lx, Ly, amp):
+    """The perturbation of Eq. 29 (section V.2) at points (x, y):
+
+      u_x =  amp Lx sin(2 pi y / Ly) sin(2 pi x / Lx)
+      u_y =  amp Ly (cos(2 pi y / Ly) - 1) cos(2 pi x / Lx)
+
+    a single x wavenumber 2 pi / Lx, divergence-free, zero at the electrodes
+    y = 0 and y = Ly; amp is the 1e-3 of Eq. 29 in the chosen velocity unit.
+    """
+    ux = amp * Lx * np.sin(2 * np.pi * y / Ly) * np.sin(2 * np.pi * x / Lx)
+    uy = amp * Ly * (np.cos(2 * np.pi * y / Ly) - 1.0) * np.cos(2 * np.pi * x / Lx)
+    return ux, uy
+
+
 def eq29_velocity(p: Params, lc):
-    """Divergence-free, no-slip perturbation of Eq. 29, in lattice velocity.
+    """Eq. 29 at the nodes, in lattice velocity.
 
     x and y in units of the gap H (x = x_node / H, y = (j + 1/2) / H), Lx =
     nx / ny, Ly = 1, amplitude 1e-3 in units of u0 = K / H.
@@ -65,10 +79,7 @@ def eq29_velocity(p: Params, lc):
     nx, ny = p.nx, p.ny
     x = (np.arange(nx) / ny)[None, :]
     y = ((np.arange(ny) + 0.5) / ny)[:, None]
-    Lx, Ly = nx / ny, 1.0
-    ux = 1e-3 * lc.u0 * Lx * np.sin(2 * np.pi * y / Ly) * np.sin(2 * np.pi * x / Lx)
-    uy = 1e-3 * lc.u0 * Ly * (np.cos(2 * np.pi * y / Ly) - 1.0) * np.cos(2 * np.pi * x / Lx)
-    return ux, uy
+    return eq29_profile(x, y, nx / ny, 1.0, 1e-3 * lc.u0)
 
 
 class Oracle:
@@ -220,14 +231,18 @@ class Oracle:
         """Nondimensional fields of the current state.
 
         rho: lattice density (drho = rho - rho_ref, the departure from the
-        hydrostatic reference row); u in u0 = K/H; rho_c in eps/H^2 (so
-        rho_c = C at the injector); phi in the applied potential difference.
+        hydrostatic reference row; rho_m1 = rho - 1, the departure from the
+        mean density, formed as (rho_ref - 1) + drho so that it keeps its
+        own relative precision: rho_ref - 1 is exact, rho_ref being within
+        a factor two of 1); u in u0 = K/H; rho_c in eps/H^2 (so rho_c = C
+        at the injector); phi in the applied potential difference.
         """
         m = self.macroscopic()
         lc = self.lc
         return dict(
             rho=m["rho"],
             drho=m["drho"],
+            rho_m1=(self.rho_ref - 1.0)[:, None] + m["drho"],
             ux=m["ux"] / lc.u0,
             uy=m["uy"] / lc.u0,
             rho_c=m["rho_c"] * lc.H**2 / lc.eps,
