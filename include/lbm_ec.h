@@ -130,9 +130,11 @@ size_t lbm_ec_workspace_bytes(const lbm_ec_params* p);
  * bytes, 256-byte aligned, on the current HIP device) and enqueues the
  * initial state on hip_stream (a hipStream_t; NULL means the null stream).
  * The initial state is step 0: the pre-collision populations are set to
- * their equilibria for the chosen init mode, the Poisson problem is solved
- * for them, and their first collision is done, as the pull-streaming time
- * loop expects.  Waits for the stream once.  The workspace must stay
+ * their equilibria (Eq. 10-11) for the chosen init mode -- the closed-form
+ * hydrostatic charge and field of section V.1 (Eq. 27-28) with seeded
+ * noise, or with the velocity perturbation of Eq. 29 (section V.2) --, the
+ * Poisson problem is solved for them, and their first collision is done, as
+ * the pull-streaming time loop expects.  Waits for the stream once.  The workspace must stay
  * allocated and untouched by the caller until lbm_ec_destroy.
  * Errors: EINVAL (bad parameters or NULL pointers), ENOMEM (ws_bytes too
  * small or misaligned), EHIP. */
@@ -148,7 +150,10 @@ int64_t lbm_ec_steps_done(const lbm_ec_t* h);
 
 /* Enqueues the conversion of the current state (after lbm_ec_steps_done
  * steps) into nondimensional FP64 fields, each a device array of ny*nx
- * doubles in row-major [y][x] order:
+ * doubles in row-major [y][x] order: the moments of the pre-collision
+ * populations (rho and rho_c by Eq. 5-6, u by Eq. 7 with half the electric
+ * force) and the potential of the Poisson solve (Eq. 4, 18-25), scaled by
+ * the groups of Eq. 26:
  *   rho   -- fluid density (lattice units, about 1)
  *   ux,uy -- velocity in units of u0 = K / H
  *   rho_c -- charge density in units of eps / H^2 (C at the injector)
@@ -156,6 +161,15 @@ int64_t lbm_ec_steps_done(const lbm_ec_t* h);
  * Any pointer may be NULL to skip that field.  Asynchronous. */
 int lbm_ec_fields(lbm_ec_t* h, double* rho, double* ux, double* uy,
                   double* rho_c, double* phi);
+
+/* The density departure rho - 1 of the current state (Eq. 5: rho is the sum
+ * of the fluid populations) into the device array rho_m1 of ny*nx doubles,
+ * [y][x].  It is formed as (rho_ref - 1) + (rho - rho_ref) from the
+ * hydrostatic reference row rho_ref(y), with no cancellation, so it keeps
+ * its own relative precision; rho - 1 taken from the rho of lbm_ec_fields
+ * loses about five digits (|rho - 1| is 1e-5 .. 1e-3).  EINVAL for a NULL
+ * pointer.  Asynchronous. */
+int lbm_ec_fields_rho_m1(lbm_ec_t* h, double* rho_m1);
 
 /* Solves the Poisson problem of Eq. 4 and 18-25 for a given charge density:
  * d_rho_c and d_phi are device arrays of ny*nx doubles, [y][x], in the
@@ -186,8 +200,10 @@ int lbm_ec_stats(lbm_ec_t* h, double* out);
  *   smaller than needed); it waits for the stream.
  *   lbm_ec_load replaces the instance's state with the checkpoint in d_src,
  *   including its step count; EINVAL unless the checkpoint was taken with the
- *   same grid, precision, charge-rate reading and physical parameters (T, C,
- *   M, Fe, tau_plus, Lambda, Lambda_g, body force).  Stepping a loaded
+ *   same grid, precision, charge-rate reading, physical parameters (T, C,
+ *   M, Fe, tau_plus, Lambda, Lambda_g, body force) and reference rows (the
+ *   stored populations are deviations from rows that are zero for an
+ *   INIT_REST start and the closed-form hydrostatic rows otherwise).  Stepping a loaded
  *   instance gives bit for bit the results the saved one would have given.
  *   It waits for the stream to read the header, then copies asynchronously.
  * Checkpoints are not portable between library versions. */
@@ -315,6 +331,9 @@ int64_t lbm_ec_batch_steps_done(lbm_ec_batch_t* b, int32_t slot);
  * step once it is done).  Asynchronous. */
 int lbm_ec_batch_fields(lbm_ec_batch_t* b, int32_t slot, double* rho, double* ux, double* uy, double* rho_c,
                         double* phi);
+
+/* As lbm_ec_fields_rho_m1, for the slot's last emitted step.  Asynchronous. */
+int lbm_ec_batch_fields_rho_m1(lbm_ec_batch_t* b, int32_t slot, double* rho_m1);
 
 /* Copies the first `rows` history rows of a slot (7 doubles each, host
  * memory); waits for the stream.  Row r holds step (r+1) * emit_every, the

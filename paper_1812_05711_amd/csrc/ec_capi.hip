@@ -964,8 +964,17 @@ int lbm_ec_batch_fields(lbm_ec_batch_t* B, int32_t slot, double* rho, double* ux
                         double* phi) {
   if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
   lbm_ec* h = &B->slots[slot].inst;
-  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, rho, ux, uy, rho_c, phi, B->s)
-                 : ec::launch_fields<double>(h->c, h->b, rho, ux, uy, rho_c, phi, B->s));
+  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, rho, ux, uy, rho_c, phi, nullptr, B->s)
+                 : ec::launch_fields<double>(h->c, h->b, rho, ux, uy, rho_c, phi, nullptr, B->s));
+  return LBM_EC_OK;
+}
+
+int lbm_ec_batch_fields_rho_m1(lbm_ec_batch_t* B, int32_t slot, double* rho_m1) {
+  if (!B || slot < 0 || slot >= B->max_slots || !B->slots[slot].used) return fail(LBM_EC_EINVAL, "bad slot");
+  if (!rho_m1) return fail(LBM_EC_EINVAL, "NULL argument");
+  lbm_ec* h = &B->slots[slot].inst;
+  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, nullptr, rho_m1, B->s)
+                 : ec::launch_fields<double>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, nullptr, rho_m1, B->s));
   return LBM_EC_OK;
 }
 
@@ -1144,8 +1153,15 @@ int64_t lbm_ec_steps_done(const lbm_ec_t* h) { return h ? h->steps : -1; }
 
 int lbm_ec_fields(lbm_ec_t* h, double* rho, double* ux, double* uy, double* rho_c, double* phi) {
   if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
-  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, rho, ux, uy, rho_c, phi, h->s)
-                 : ec::launch_fields<double>(h->c, h->b, rho, ux, uy, rho_c, phi, h->s));
+  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, rho, ux, uy, rho_c, phi, nullptr, h->s)
+                 : ec::launch_fields<double>(h->c, h->b, rho, ux, uy, rho_c, phi, nullptr, h->s));
+  return LBM_EC_OK;
+}
+
+int lbm_ec_fields_rho_m1(lbm_ec_t* h, double* rho_m1) {
+  if (!h || !rho_m1) return fail(LBM_EC_EINVAL, "NULL argument");
+  EC_HIP(h->fp32 ? ec::launch_fields<float>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, nullptr, rho_m1, h->s)
+                 : ec::launch_fields<double>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, nullptr, rho_m1, h->s));
   return LBM_EC_OK;
 }
 
@@ -1155,11 +1171,11 @@ int lbm_ec_poisson(lbm_ec_t* h, const double* d_rho_c, double* d_phi) {
   if (h->fp32) {
     EC_HIP(ec::launch_charge_in<float>(h->c, h->b, d_rho_c, h->s));
     if ((rc = poisson_chain<float>(h, 2, 0))) return rc;
-    EC_HIP(ec::launch_fields<float>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, d_phi, h->s));
+    EC_HIP(ec::launch_fields<float>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, d_phi, nullptr, h->s));
   } else {
     EC_HIP(ec::launch_charge_in<double>(h->c, h->b, d_rho_c, h->s));
     if ((rc = poisson_chain<double>(h, 2, 0))) return rc;
-    EC_HIP(ec::launch_fields<double>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, d_phi, h->s));
+    EC_HIP(ec::launch_fields<double>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, d_phi, nullptr, h->s));
   }
   return LBM_EC_OK;
 }
@@ -1221,6 +1237,9 @@ struct CkptHeader {
   char magic[8];
   uint32_t version, header_bytes;
   int32_t nx, ny, precision, charge_rates;
+  // the reference rows of the stored deviations: zero for a rest start,
+  // the closed-form hydrostatic rows otherwise
+  int32_t rest_rows, pad;
   double T, C, M, Fe, tau_plus, Lambda, Lambda_g, body_force_x;
   int64_t steps;
   uint64_t total;
@@ -1262,13 +1281,14 @@ CkptLayout ckpt_layout(const lbm_ec* h) {
 void ckpt_fill(const lbm_ec* h, CkptHeader* H, uint64_t total) {
   std::memset(H, 0, sizeof(*H));
   std::memcpy(H->magic, kCkptMagic, 8);
-  H->version = 2;
+  H->version = 3;
   H->header_bytes = (uint32_t)sizeof(CkptHeader);
   const lbm_ec_params& p = h->p;
   H->nx = p.nx;
   H->ny = p.ny;
   H->precision = p.precision;
   H->charge_rates = p.charge_rates;
+  H->rest_rows = p.init_mode == LBM_EC_INIT_REST ? 1 : 0;
   H->T = p.T;
   H->C = p.C;
   H->M = p.M;
@@ -1314,11 +1334,12 @@ int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes) {
   EC_HIP(hipMemcpyAsync(&H, d, sizeof(H), hipMemcpyDeviceToHost, h->s));
   EC_HIP(hipStreamSynchronize(h->s));
   ckpt_fill(h, &mine, K.total);
-  if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 2 || H.header_bytes != sizeof(CkptHeader))
+  if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 3 || H.header_bytes != sizeof(CkptHeader))
     return fail(LBM_EC_EINVAL, "not a checkpoint of this library version");
   mine.steps = H.steps;
   if (std::memcmp(&H, &mine, sizeof(H)) != 0)
-    return fail(LBM_EC_EINVAL, "checkpoint taken with other grid, precision or physical parameters");
+    return fail(LBM_EC_EINVAL,
+                "checkpoint taken with other grid, precision, physical parameters or reference rows (rest start)");
   h->cur = 0;
   EC_HIP(hipMemcpyAsync(h->b.f[0], d + K.off_f, K.pop, hipMemcpyDeviceToDevice, h->s));
   EC_HIP(hipMemcpyAsync(h->b.g[0], d + K.off_g, K.pop, hipMemcpyDeviceToDevice, h->s));

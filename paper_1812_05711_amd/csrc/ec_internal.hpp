@@ -212,7 +212,7 @@ hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, 
                           const Tuning& tu, hipStream_t s);
 template <typename T>
 hipError_t launch_fields(const Consts& c, const Bufs& b, double* rho, double* ux, double* uy,
-                         double* rho_c, double* phi, hipStream_t s);
+                         double* rho_c, double* phi, double* rho_m1, hipStream_t s);
 template <typename T>
 hipError_t launch_charge_in(const Consts& c, const Bufs& b, const double* rho_c_nd, hipStream_t s);
 // cur: the buffer holding the post-collision populations (boundary charge)

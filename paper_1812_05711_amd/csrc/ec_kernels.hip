@@ -1517,16 +1517,19 @@ __global__ void __launch_bounds__(256) k_init_populations(Consts c, T* __restric
   }
 }
 
-// Nondimensional FP64 output fields of the current state.
+// Nondimensional FP64 output fields of the current state.  rho_m1 = rho - 1
+// as (rho_ref - 1) + (rho - rho_ref): rho_ref - 1 is exact (rho_ref lies
+// within a factor two of 1), so the departure keeps its relative precision.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fields(Consts c, const double* __restrict__ mom, const T* __restrict__ phi,
                                                 const double* __restrict__ rowsd, double* rho, double* ux,
-                                                double* uy, double* rho_c, double* phio) {
+                                                double* uy, double* rho_c, double* phio, double* rho_m1) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (x >= c.nx) return;
   const size_t n = (size_t)c.ny * c.nx, k = (size_t)j * c.nx + x;
   if (rho) rho[k] = rowsd[ROWD_RHO_REF * c.ny + j] + mom[k];
+  if (rho_m1) rho_m1[k] = (rowsd[ROWD_RHO_REF * c.ny + j] - 1.0) + mom[k];
   if (ux) ux[k] = mom[n + k] / c.u0;
   if (uy) uy[k] = mom[2 * n + k] / c.u0;
   if (rho_c) rho_c[k] = (rowsd[ROWD_R * c.ny + j] + mom[3 * n + k]) * c.H * c.H / c.eps;
@@ -1983,9 +1986,10 @@ hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, 
 
 template <typename T>
 hipError_t launch_fields(const Consts& c, const Bufs& b, double* rho, double* ux, double* uy, double* rho_c,
-                         double* phi, hipStream_t s) {
+                         double* phi, double* rho_m1, hipStream_t s) {
   dim3 blk(256), grd((c.nx + 255) / 256, c.ny);
-  hipLaunchKernelGGL(k_fields<T>, grd, blk, 0, s, c, b.mom, (const T*)b.phi, b.rowsd, rho, ux, uy, rho_c, phi);
+  hipLaunchKernelGGL(k_fields<T>, grd, blk, 0, s, c, b.mom, (const T*)b.phi, b.rowsd, rho, ux, uy, rho_c, phi,
+                     rho_m1);
   return hipGetLastError();
 }
 
@@ -2044,7 +2048,7 @@ hipError_t launch_density(const Consts& c, const Bufs& b, int cur, const Tuning&
   template hipError_t launch_tridiag<T>(const Consts&, const Bufs&, hipStream_t);                           \
   template hipError_t launch_inverse<T>(const Consts&, const Bufs&, const FftPlan&, const Tuning&, hipStream_t); \
   template hipError_t launch_fields<T>(const Consts&, const Bufs&, double*, double*, double*, double*,       \
-                                       double*, hipStream_t);                                               \
+                                       double*, double*, hipStream_t);                                      \
   template hipError_t launch_charge_in<T>(const Consts&, const Bufs&, const double*, hipStream_t);          \
   template hipError_t launch_stats<T>(const Consts&, const Bufs&, int, hipStream_t);                        \
   template hipError_t launch_continue<T>(const Consts&, const Bufs&, int, double, double, hipStream_t);     \

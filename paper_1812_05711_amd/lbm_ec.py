@@ -85,6 +85,8 @@ def lib():
     L.lbm_ec_steps_done.restype = ctypes.c_int64
     L.lbm_ec_fields.argtypes = [vp, vp, vp, vp, vp, vp]
     L.lbm_ec_fields.restype = ctypes.c_int
+    L.lbm_ec_fields_rho_m1.argtypes = [vp, vp]
+    L.lbm_ec_fields_rho_m1.restype = ctypes.c_int
     L.lbm_ec_poisson.argtypes = [vp, vp, vp]
     L.lbm_ec_poisson.restype = ctypes.c_int
     L.lbm_ec_stats.argtypes = [vp, dp]
@@ -114,6 +116,8 @@ def lib():
     L.lbm_ec_batch_steps_done.restype = ctypes.c_int64
     L.lbm_ec_batch_fields.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.lbm_ec_batch_fields.restype = ctypes.c_int
+    L.lbm_ec_batch_fields_rho_m1.argtypes = [vp, i32, vp]
+    L.lbm_ec_batch_fields_rho_m1.restype = ctypes.c_int
     L.lbm_ec_batch_history.argtypes = [vp, i32, dp, i32]
     L.lbm_ec_batch_history.restype = ctypes.c_int
     L.lbm_ec_batch_release.argtypes = [vp, i32]
@@ -205,11 +209,13 @@ class Simulation:
         return int(lib().lbm_ec_steps_done(self._h))
 
     def fields(self):
-        """Dict of nondimensional FP64 device tensors (ny, nx): rho, ux, uy, rho_c, phi."""
+        """Dict of nondimensional FP64 device tensors (ny, nx): rho, ux, uy,
+        rho_c, phi, and rho_m1 = rho - 1 (lbm_ec_fields_rho_m1)."""
         out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
-               for k in ("rho", "ux", "uy", "rho_c", "phi")}
+               for k in ("rho", "ux", "uy", "rho_c", "phi", "rho_m1")}
         _check(lib().lbm_ec_fields(self._h, *[ctypes.c_void_p(out[k].data_ptr())
                                               for k in ("rho", "ux", "uy", "rho_c", "phi")]))
+        _check(lib().lbm_ec_fields_rho_m1(self._h, ctypes.c_void_p(out["rho_m1"].data_ptr())))
         return out
 
     def poisson(self, rho_c: torch.Tensor) -> torch.Tensor:
@@ -348,9 +354,10 @@ class Batch:
     def fields(self, slot):
         ny, nx = self._shape[slot]
         out = {k: torch.empty((ny, nx), dtype=torch.float64, device=self.device)
-               for k in ("rho", "ux", "uy", "rho_c", "phi")}
+               for k in ("rho", "ux", "uy", "rho_c", "phi", "rho_m1")}
         _check(lib().lbm_ec_batch_fields(self._h, int(slot), *[ctypes.c_void_p(out[k].data_ptr())
                                                                for k in ("rho", "ux", "uy", "rho_c", "phi")]))
+        _check(lib().lbm_ec_batch_fields_rho_m1(self._h, int(slot), ctypes.c_void_p(out["rho_m1"].data_ptr())))
         self.stream.synchronize()
         return out
 

@@ -9,7 +9,9 @@ per kernel type, replayed from captured graphs), polls for finished
 requests, releases their slots and records the latency from arrival to the
 moment the final fields are ready on the device.  Requests that arrive while
 others run join at the next chunk boundary, so their work overlaps on the
-device; each one computes exactly what it would compute alone.
+device; each one computes exactly what it would compute alone.  A request
+whose footprint exceeds the whole budget is refused (listed in the
+summary) rather than waited for.
 """
 
 import collections
@@ -82,6 +84,7 @@ def serve(requests, backend, chunk=100, warmup=0, clock=time.perf_counter, sleep
     waiting = collections.deque()
     running = {}
     records = []
+    refused = []
     queued_max = 0
     t0 = clock()
     while pending or waiting or running:
@@ -94,7 +97,13 @@ def serve(requests, backend, chunk=100, warmup=0, clock=time.perf_counter, sleep
             req = waiting[0]
             slot = backend.admit(req)
             if slot is None:
-                break  # no slot or no room: wait for a release
+                if running:
+                    break  # no slot or no room: wait for a release
+                # nothing runs, so the whole budget is free: this request
+                # can never be admitted
+                waiting.popleft()
+                refused.append(req["id"])
+                continue
             waiting.popleft()
             req["admitted"] = clock() - t0
             running[slot] = req
@@ -118,6 +127,6 @@ def serve(requests, backend, chunk=100, warmup=0, clock=time.perf_counter, sleep
                    p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
                    p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
                    mean_s=float(lat.mean()) if len(lat) else None,
-                   mlups=node_steps / wall / 1e6, max_queue=queued_max,
+                   mlups=node_steps / wall / 1e6, max_queue=queued_max, refused=refused,
                    unhealthy=sum(1 for r in records if r.get("healthy") is False))
     return records, summary

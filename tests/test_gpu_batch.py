@@ -73,7 +73,7 @@ def test_batch_slot_matches_oracle():
     assert set(b.poll()) == {s, other}
     got = {k: v.cpu().numpy() for k, v in b.fields(s).items()}
     e = errors(got, oracle_fields(kw, n))
-    assert max(e["rho"], e["u"], e["rho_c"], e["phi"]) <= 1e-11, e
+    assert max(e["rho"], e["rho_m1"], e["u"], e["rho_c"], e["phi"]) <= 1e-11, e
     b.close()
 
 

@@ -65,6 +65,27 @@ def test_load_refuses_other_parameters():
     a.close()
 
 
+def test_load_refuses_other_reference_rows():
+    """The stored populations are deviations from reference rows that are
+    zero for a rest start and hydrostatic otherwise: a checkpoint of one kind
+    is refused by an instance of the other (same grid and parameters), in
+    both directions; the same kind loads."""
+    from paper_1812_05711_amd.lbm_ec import LbmEcError, Simulation
+
+    kw = dict(BASE, nx=32, ny=20)
+    rest = Simulation(device="cuda:0", **dict(kw, init_mode="rest"))
+    noise = Simulation(device="cuda:0", **kw)
+    eq29 = Simulation(device="cuda:0", **dict(kw, init_mode="eq29"))
+    ck_rest, ck_noise = rest.save(), noise.save()
+    with pytest.raises(LbmEcError):
+        noise.load(ck_rest)
+    with pytest.raises(LbmEcError):
+        rest.load(ck_noise)
+    eq29.load(ck_noise)  # both carry the hydrostatic rows
+    for s in (rest, noise, eq29):
+        s.close()
+
+
 def test_electrode_fluxes_match_oracle_and_charge_balance():
     from paper_1812_05711_amd.lbm_ec import Simulation
 

@@ -72,7 +72,7 @@ def test_set_T_matches_oracle(nx, ny, sched, precision):
     assert g["steps"] == sum(n for n, _ in schedule)
     e = errors(g, o.fields())
     print({k: f"{v:.2e}" for k, v in e.items()}, flush=True)
-    for k in ("rho", "u", "rho_c", "phi"):
+    for k in ("rho", "rho_m1", "u", "rho_c", "phi"):
         assert e[k] <= TOL[precision], (k, e)
     inj, col = o.electrode_currents()
     assert abs(st["q_injector"] - inj) <= TOL_CUR[precision] * abs(inj), (st["q_injector"], inj)

@@ -94,3 +94,33 @@ def test_fifo_admission_by_footprint_and_latency():
         assert r["latency"] >= 0 and r["admitted"] >= r["arrival"] and r["done"] >= r["admitted"]
     assert summary["max_queue"] > 0  # the budget made requests wait
     assert summary["requests"] == 60 and summary["p99_s"] >= summary["p50_s"] > 0
+
+
+def test_request_larger_than_the_budget_is_refused():
+    """A request whose footprint exceeds the whole budget can never be
+    admitted: it is refused once nothing runs, and the loop still ends."""
+    reqs = make_requests(12, rate=100.0, seed=7, steps=200)
+    clock = FakeClock()
+    big = max(reqs, key=lambda r: r["params"]["nx"] * r["params"]["ny"])
+    be = FakeBackend(budget=be_bytes(big) - 1, max_slots=4)
+
+    class Timed:
+        def __init__(self, inner):
+            self.inner = inner
+
+        def __getattr__(self, k):
+            return getattr(self.inner, k)
+
+        def step(self, n):
+            self.inner.step(n)
+            clock.t += 1e-3 * n / 100
+
+    records, summary = serve(reqs, Timed(be), chunk=100, clock=clock, sleep=clock.sleep, max_wall=1e3)
+    too_big = sorted(r["id"] for r in reqs if be.footprint(r) > be.budget)
+    assert too_big and summary["refused"] == too_big
+    assert sorted(r["id"] for r in records) == sorted(set(range(12)) - set(too_big))
+    assert be.used == 0 and not be.slots
+
+
+def be_bytes(req, bytes_per_node=164):
+    return req["params"]["nx"] * req["params"]["ny"] * bytes_per_node
