@@ -178,6 +178,36 @@ int lbm_ec_fields_rho_m1(lbm_ec_t* h, double* rho_m1);
  * only for testing).  Asynchronous. */
 int lbm_ec_poisson(lbm_ec_t* h, const double* d_rho_c, double* d_phi);
 
+/* Size of the device scratch of lbm_ec_poisson_static (64 MiB), a static
+ * array of the library that each GPU it runs on holds until the process
+ * ends. */
+#define LBM_EC_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* The Poisson solve of lbm_ec_poisson for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): no handle and no workspace.  It solves the problem
+ * of the grid and lattice constants of *p (nx, ny, and the permittivity
+ * (M K)^2 from T, M, tau_plus; reference rows as for p->init_mode) for the
+ * nondimensional charge density d_rho_c and writes the potential to d_phi
+ * (device arrays of ny*nx doubles, [y][x], units of lbm_ec_fields), with the
+ * same kernels, tables and launch shapes as lbm_ec_poisson on an instance of
+ * the same parameters, so the same result bit for bit.  Its scratch is a
+ * file-scope device array of LBM_EC_STATIC_SCRATCH_BYTES, one per GPU: the
+ * call allocates no device memory (the tables are copied into the scratch
+ * from host memory, and the call waits for the stream once for that).  Every
+ * call on a GPU shares that GPU's scratch and leaves its contents behind
+ * (no part of the solve reads what an earlier call left); calls that overlap
+ * on one GPU (other host threads, other streams) race and must be serialised
+ * by the caller.  Asynchronous after the table copy, on hip_stream (NULL: the
+ * null stream) of the current device.
+ * Errors: EINVAL for NULL pointers, invalid parameters or a grid whose
+ * scratch (lbm_ec_poisson_static_bytes) exceeds LBM_EC_STATIC_SCRATCH_BYTES;
+ * EHIP. */
+int lbm_ec_poisson_static(const lbm_ec_params* p, const double* d_rho_c, double* d_phi, void* hip_stream);
+
+/* Scratch bytes lbm_ec_poisson_static needs for *p (0 if p is invalid). */
+size_t lbm_ec_poisson_static_bytes(const lbm_ec_params* p);
+
 /* Global diagnostics of the current state, computed in FP64 on the device
  * and copied to host memory out[10] (waits for the stream):
  *   out[0] steps done, out[1] sum of (rho - 1) over nodes, out[2] sum of

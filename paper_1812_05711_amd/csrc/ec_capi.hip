@@ -5,11 +5,16 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/lbm_ec.h"
 #include "ec_internal.hpp"
+
+// Scratch of lbm_ec_poisson_static (see there): one copy per GPU.
+constexpr size_t kStaticScratchBytes = (size_t)LBM_EC_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -100,7 +105,9 @@ struct Layout {
       off_rowsd, off_dmean, off_mom, off_stats, off_spart, total;
 };
 
-Layout make_layout(const lbm_ec_params& p) {
+// poisson_only: the buffers of the Poisson chain alone (no populations, no
+// charge sums of the collide tiles), for lbm_ec_poisson_static.
+Layout make_layout(const lbm_ec_params& p, bool poisson_only = false) {
   Layout L{};
   L.tsize = p.precision == LBM_EC_FP64 ? 8 : 4;
   const int elems = (int)(256 / L.tsize);  // pitch multiple of 256 bytes
@@ -120,14 +127,14 @@ Layout make_layout(const lbm_ec_params& p) {
     o = align_up(o + bytes);
     return at;
   };
-  const size_t pop = 9 * ny * L.P * L.tsize;
+  const size_t pop = poisson_only ? 0 : 9 * ny * L.P * L.tsize;
   L.off_f[0] = take(pop);
   L.off_f[1] = take(pop);
   L.off_g[0] = take(pop);
   L.off_g[1] = take(pop);
   L.off_phi = take(ny * L.P * L.tsize);
-  const size_t tiles = (ny + ec::tile_rows(p.ny) - 1) / ec::tile_rows(p.ny);
-  L.off_rq = take(ny * L.P * L.tsize);
+  const size_t tiles = poisson_only ? 0 : (ny + ec::tile_rows(p.ny) - 1) / ec::tile_rows(p.ny);
+  L.off_rq = take(poisson_only ? 0 : ny * L.P * L.tsize);
   L.off_eu = take(tiles * L.P * L.tsize);
   L.off_ed = take(tiles * L.P * L.tsize);
   L.off_spec = take(ny * L.MP * 2 * L.tsize);
@@ -545,10 +552,8 @@ int run_steps(lbm_ec* h, int64_t n) {
   return LBM_EC_OK;
 }
 
-// Builds an instance in the device region ws (L.total bytes) on stream s and
-// enqueues its initial state; waits for the stream.
-int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStream_t s) {
-  const Layout L = make_layout(*p);
+// Points the handle at the buffers of layout L inside the device region ws.
+void bind_buffers(lbm_ec* h, const lbm_ec_params* p, const Layout& L, unsigned char* ws, hipStream_t s) {
   h->p = *p;
   h->L = L;
   h->s = s;
@@ -579,6 +584,12 @@ int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStre
   h->b.mom = (double*)(ws + L.off_mom);
   h->b.stats = (double*)(ws + L.off_stats);
   h->b.spart = (double*)(ws + L.off_spart);
+}
+
+// Builds an instance in the device region ws (L.total bytes) on stream s and
+// enqueues its initial state; waits for the stream.
+int build_instance(lbm_ec* h, const lbm_ec_params* p, unsigned char* ws, hipStream_t s) {
+  bind_buffers(h, p, make_layout(*p), ws, s);
   int rc = h->fp32 ? setup<float>(h, ws) : setup<double>(h, ws);
   if (!rc) {
     if (p->precision == LBM_EC_FP64)
@@ -1352,6 +1363,75 @@ int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes) {
   EC_HIP(hipMemcpyAsync(h->b.mom, d + K.off_mom, K.mom, hipMemcpyDeviceToDevice, h->s));
   h->steps = H.steps;
   return LBM_EC_OK;
+}
+
+// ------------------------------------------- Poisson solve without allocation
+// The scratch of lbm_ec_poisson_static: the Poisson-only layout of one grid
+// (spectrum, potential, chunk and interface tables, twiddles, row tables, the
+// charge field).  A file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never passes its name to a kernel or a copy: the
+// name is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device.
+}  // extern "C"
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up on first use).
+int static_scratch(void** out) {
+  int dev = -1;
+  EC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EC_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_EC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_EC_OK;
+}
+
+// The Poisson chain of lbm_ec_poisson on a handle whose buffers live in the
+// scratch: same plan, tables, launch shapes and kernels, so the same result.
+template <typename T>
+int poisson_in_scratch(lbm_ec* h, unsigned char* ws, const double* d_rho_c, double* d_phi) {
+  int rc = setup<T>(h, ws, false);  // tables only: nothing of the chain must start at zero
+  if (rc) return rc;
+  EC_HIP(ec::launch_charge_in<T>(h->c, h->b, d_rho_c, h->s));
+  if ((rc = poisson_chain<T>(h, 2, 0))) return rc;
+  EC_HIP(ec::launch_fields<T>(h->c, h->b, nullptr, nullptr, nullptr, nullptr, d_phi, nullptr, h->s));
+  return LBM_EC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t lbm_ec_poisson_static_bytes(const lbm_ec_params* p) {
+  if (validate(p) != LBM_EC_OK) return 0;
+  return make_layout(*p, true).total;
+}
+
+int lbm_ec_poisson_static(const lbm_ec_params* p, const double* d_rho_c, double* d_phi, void* hip_stream) {
+  g_err.clear();
+  if (!p || !d_rho_c || !d_phi) return fail(LBM_EC_EINVAL, "NULL argument");
+  int rc = validate(p);
+  if (rc) return rc;
+  const Layout L = make_layout(*p, true);
+  if (L.total > kStaticScratchBytes)
+    return fail(LBM_EC_EINVAL, "grid needs " + std::to_string(L.total) + " bytes of Poisson scratch; the static scratch holds " +
+                                   std::to_string(kStaticScratchBytes));
+  void* ptr = nullptr;
+  if ((rc = static_scratch(&ptr))) return rc;
+  lbm_ec h{};
+  unsigned char* ws = (unsigned char*)ptr;
+  bind_buffers(&h, p, L, ws, (hipStream_t)hip_stream);
+  return h.fp32 ? poisson_in_scratch<float>(&h, ws, d_rho_c, d_phi)
+                : poisson_in_scratch<double>(&h, ws, d_rho_c, d_phi);
 }
 
 // Test hook of the failure detection: a NaN in one population of the current

@@ -89,6 +89,10 @@ def lib():
     L.lbm_ec_fields_rho_m1.restype = ctypes.c_int
     L.lbm_ec_poisson.argtypes = [vp, vp, vp]
     L.lbm_ec_poisson.restype = ctypes.c_int
+    L.lbm_ec_poisson_static.argtypes = [P, vp, vp, vp]
+    L.lbm_ec_poisson_static.restype = ctypes.c_int
+    L.lbm_ec_poisson_static_bytes.argtypes = [P]
+    L.lbm_ec_poisson_static_bytes.restype = ctypes.c_size_t
     L.lbm_ec_stats.argtypes = [vp, dp]
     L.lbm_ec_stats.restype = ctypes.c_int
     L.lbm_ec_profile_begin.argtypes = [vp, ctypes.c_uint32]
@@ -176,6 +180,35 @@ def workspace_bytes(p: Params) -> int:
     if n == 0:
         _check(lib().lbm_ec_validate(ctypes.byref(p)))
     return n
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # LBM_EC_STATIC_SCRATCH_BYTES
+
+
+def poisson_static_bytes(**kw) -> int:
+    """Scratch bytes lbm_ec_poisson_static needs for these parameters."""
+    return int(lib().lbm_ec_poisson_static_bytes(ctypes.byref(make_params(**kw))))
+
+
+def poisson_static(rho_c: torch.Tensor, out: torch.Tensor = None, stream=None, **kw) -> torch.Tensor:
+    """phi for a nondimensional charge density (ny, nx) through
+    lbm_ec_poisson_static, which allocates no device memory: its scratch is a
+    static array of the library.  `out` (a float64 (ny, nx) device tensor)
+    receives phi; allocate it beforehand to keep the whole call free of
+    allocations.  kw: the parameters of make_params (nx, ny, T, M, tau_plus,
+    init_mode, precision ...)."""
+    p = make_params(**kw)
+    assert rho_c.is_cuda and rho_c.dtype == torch.float64 and rho_c.is_contiguous()
+    assert tuple(rho_c.shape) == (p.ny, p.nx)
+    if out is None:
+        out = torch.empty_like(rho_c)
+    assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.shape == rho_c.shape
+    if stream is None:
+        stream = torch.cuda.current_stream(rho_c.device)
+    with torch.cuda.device(rho_c.device):
+        _check(lib().lbm_ec_poisson_static(ctypes.byref(p), ctypes.c_void_p(rho_c.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+    return out
 
 
 class Simulation:
