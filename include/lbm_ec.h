@@ -114,9 +114,10 @@ typedef struct lbm_ec lbm_ec_t;
  * noise_amp = 1e-3, seed = 181205711.  Returns EINVAL if p is NULL. */
 int lbm_ec_params_default(lbm_ec_params* p);
 
-/* Checks a parameter set (see the field comments; also nx within the
- * widest grid of the chosen precision: 2048 in FP64, 4096 with FP32 storage,
- * since a collide tile holds ten rows of nx values in LDS; every real
+/* Checks a parameter set (see the field comments; also nx <= 8192 with the
+ * x transform of a row pair fitting one workgroup's LDS at 512 threads: any
+ * nx up to 8192 in FP32 storage, and in FP64 up to 8192 when nx has no prime
+ * factor above 5 (in-place transforms), up to 5120 otherwise; every real
  * parameter finite; and the lattice mobility K = nu T / M^2, permittivity
  * eps = (M K)^2, injected charge rho0 = C eps / ny^2 and diffusivity
  * D_c = K / Fe finite, with K, eps and D_c positive).  Returns OK or
@@ -290,14 +291,22 @@ int lbm_ec_profile_begin(lbm_ec_t* h, uint32_t class_mask);
 int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n);
 
 /* Launch shapes, which never change results: threads per x-transform block
- * (64, 128, 256 or 512) and threads per collide tile (collide_bx *
- * collide_by, a multiple of 64 up to 1024; a tile is a band of whole rows
- * whose height depends on ny only).  Defaults: about nx / 8 transform
- * threads (64 .. 512) and nx rounded up to 64 collide threads (at most 1024)
- * for a single instance; 256 and 256 x 1 for a batch.  Applies to
- * the following steps; EINVAL for other values.  The autotuner in
+ * (64, 128, 256 or 512; EINVAL when a row pair's transform would then need
+ * more than 160 KiB of LDS), threads per collide tile (collide_bx *
+ * collide_by, a multiple of 64 up to 1024) and columns per collide tile
+ * (collide_tw, 1 .. 1024, or 0 for the default: whole rows while ten rows
+ * of them fit 160 KiB of LDS -- nx <= 4096 in FP32 storage, 2048 in FP64 --
+ * and 1024-column tiles beyond).  A collide tile is a band of rows whose
+ * height depends on ny only, and of collide_tw columns; a tile narrower than
+ * the row also collides the two columns next to it (without storing them),
+ * so every node's charge sum is formed from the same values in the same
+ * order whatever the width.  Defaults: about nx / 8 transform threads
+ * (64 .. 512) and nx rounded up to 64 collide threads (at most 1024) for a
+ * single instance; 256 and 256 x 1 for a batch.  Applies to the following
+ * steps; EINVAL for other values.  The autotuner in
  * paper_1812_05711_amd/autotune.py picks them by timing. */
-int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by);
+int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by,
+                      int32_t collide_tw);
 
 /* Releases the handle (host memory only; the caller frees the workspace). */
 void lbm_ec_destroy(lbm_ec_t* h);
@@ -377,8 +386,10 @@ int lbm_ec_batch_history(lbm_ec_batch_t* b, int32_t slot, double* out, int32_t r
 int lbm_ec_batch_set_T(lbm_ec_batch_t* b, int32_t slot, double T);
 
 /* Launch shapes for the batch's kernels (as lbm_ec_set_tuning); the graphs
- * are re-captured at the next step. */
-int lbm_ec_batch_set_tuning(lbm_ec_batch_t* b, int32_t fft_threads, int32_t collide_bx, int32_t collide_by);
+ * are re-captured at the next step, which returns EINVAL if a slot's
+ * transform does not fit LDS with these shapes. */
+int lbm_ec_batch_set_tuning(lbm_ec_batch_t* b, int32_t fft_threads, int32_t collide_bx, int32_t collide_by,
+                            int32_t collide_tw);
 
 /* Frees a slot and its workspace region (waits for the stream). */
 int lbm_ec_batch_release(lbm_ec_batch_t* b, int32_t slot);

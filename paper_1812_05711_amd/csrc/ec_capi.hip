@@ -37,9 +37,9 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Widest grid: a collide tile holds ten rows of nx values of the storage
-// type in LDS, at most 160 KiB per workgroup.
-int max_nx(int precision) { return precision == LBM_EC_FP64 ? 2048 : 4096; }
+// Widest grid: a row pair's x transform is held in LDS (at most 160 KiB per
+// workgroup); collide tiles are at most ec::kTileW columns wide whatever nx.
+constexpr int kMaxNx = 8192;
 
 // v rounded to `bits` significant bits, ties to even.
 double round_bits(double v, int bits) {
@@ -155,14 +155,20 @@ Layout make_layout(const lbm_ec_params& p, bool poisson_only = false) {
   return L;
 }
 
+// LDS of one x-transform block of `threads` threads for rows of nx.
+size_t transform_lds(int nx, int precision, int threads) {
+  const ec::FftPlan pl = make_plan(nx);
+  return precision == LBM_EC_FP64 ? ec::fft_lds_bytes<double>(pl, threads) : ec::fft_lds_bytes<float>(pl, threads);
+}
+
 int validate(const lbm_ec_params* p) {
   if (!p) return fail(LBM_EC_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 3) return fail(LBM_EC_EINVAL, "grid must have nx >= 1 and ny >= 3");
   if (p->precision != LBM_EC_FP64 && p->precision != LBM_EC_FP32_DEV && p->precision != LBM_EC_FP32_DEV_F64MATH)
     return fail(LBM_EC_EINVAL, "unknown precision");
-  if (p->nx > max_nx(p->precision))
-    return fail(LBM_EC_EINVAL, "nx exceeds the x-transform limit (" + std::to_string(max_nx(p->precision)) +
-                                   ") of this precision");
+  if (p->nx > kMaxNx) return fail(LBM_EC_EINVAL, "nx exceeds " + std::to_string(kMaxNx));
+  if (transform_lds(p->nx, p->precision, 512) > ec::kMaxLds)
+    return fail(LBM_EC_EINVAL, "the x transform of this nx does not fit LDS in this precision");
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_EC_EINVAL, "grid too large");
   if (!(p->tau_plus > 0.5) || !std::isfinite(p->tau_plus)) return fail(LBM_EC_EINVAL, "tau_plus must exceed 1/2");
   if (!(p->Lambda > 0) || !(p->Lambda_g > 0) || !std::isfinite(p->Lambda) || !std::isfinite(p->Lambda_g))
@@ -331,6 +337,7 @@ int setup(lbm_ec* h, unsigned char* ws, bool fresh = true) {
   c.NC = L.NC;
   c.KP = L.KP;
   c.TH = ec::tile_rows(ny);
+  c.TW = ec::tile_width(nx, h->tu.ctw, (int)sizeof(T));
   c.wp = 1.0 / p.tau_plus;
   c.wm = 1.0 / tau_m;
   c.wgp = 1.0 / tau_gp;
@@ -795,6 +802,7 @@ int rebuild(lbm_ec_batch* B) {
     Slot& sl = B->slots[B->order[q]];
     ec::SlotDesc& d = D[q];
     d.c = sl.inst.c;
+    d.c.TW = ec::tile_width(d.c.nx, B->tu.ctw, sl.inst.fp32 ? 4 : 8);
     d.b = sl.inst.b;
     d.plan = sl.inst.plan;
     d.cur = sl.inst.cur;
@@ -807,8 +815,8 @@ int rebuild(lbm_ec_batch* B) {
     const size_t lds = sl.inst.fp32 ? ec::fft_lds_bytes<float>(sl.inst.plan, B->tu.fft_threads)
                                     : ec::fft_lds_bytes<double>(sl.inst.plan, B->tu.fft_threads);
     B->lds = std::max(B->lds, lds);
-    const size_t clds = sl.inst.fp32 ? ec::collide_lds_bytes<float>(sl.inst.p.nx)
-                                     : ec::collide_lds_bytes<double>(sl.inst.p.nx);
+    const size_t clds = sl.inst.fp32 ? ec::collide_lds_bytes<float>(d.c.TW, d.c.nx)
+                                     : ec::collide_lds_bytes<double>(d.c.TW, d.c.nx);
     B->collide_lds = std::max(B->collide_lds, clds);
     B->fft8 = B->fft8 && ec::fft_in_place(sl.inst.plan, B->tu.fft_threads, 8);
     for (int k = 0; k < ec::BK_COUNT; ++k) {
@@ -817,6 +825,8 @@ int rebuild(lbm_ec_batch* B) {
     }
   }
   for (int k = 0; k < ec::BK_COUNT; ++k) off[(size_t)k * (ns + 1) + ns] = B->totals[k];
+  if (B->lds > ec::kMaxLds || B->collide_lds > ec::kMaxLds)
+    return fail(LBM_EC_EINVAL, "launch shapes too small for the widest slot (LDS of a block beyond 160 KiB)");
   if (ns) {
     EC_HIP(hipMemcpyAsync(B->d_desc, D.data(), sizeof(ec::SlotDesc) * ns, hipMemcpyHostToDevice, B->s));
     EC_HIP(hipMemcpyAsync(B->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, B->s));
@@ -1041,32 +1051,39 @@ void lbm_ec_batch_destroy(lbm_ec_batch_t* B) {
   delete B;
 }
 
-static int check_tuning(int32_t fft_threads, int32_t bx, int32_t by) {
+static int check_tuning(int32_t fft_threads, int32_t bx, int32_t by, int32_t tw) {
   if (fft_threads != 64 && fft_threads != 128 && fft_threads != 256 && fft_threads != 512)
     return fail(LBM_EC_EINVAL, "fft_threads must be 64, 128, 256 or 512");
   const int64_t t = (int64_t)bx * by;
   if (bx < 1 || by < 1 || t % 64 != 0 || t > 1024)
     return fail(LBM_EC_EINVAL, "collide block bx * by must be a multiple of 64 up to 1024");
+  if (tw < 0 || tw > ec::kTileW) return fail(LBM_EC_EINVAL, "collide tile width must be 0 (default) .. 1024");
   return LBM_EC_OK;
 }
 
-int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by) {
+int lbm_ec_set_tuning(lbm_ec_t* h, int32_t fft_threads, int32_t collide_bx, int32_t collide_by, int32_t collide_tw) {
   if (!h) return fail(LBM_EC_EINVAL, "handle is NULL");
-  int rc = check_tuning(fft_threads, collide_bx, collide_by);
+  int rc = check_tuning(fft_threads, collide_bx, collide_by, collide_tw);
   if (rc) return rc;
+  if (transform_lds(h->p.nx, h->p.precision, fft_threads) > ec::kMaxLds)
+    return fail(LBM_EC_EINVAL, "too few transform threads for this nx (LDS of a block beyond 160 KiB)");
   h->tu.fft_threads = fft_threads;
   h->tu.cbx = collide_bx;
   h->tu.cby = collide_by;
+  h->tu.ctw = collide_tw;
+  h->c.TW = ec::tile_width(h->p.nx, collide_tw, h->fp32 ? 4 : 8);
   return LBM_EC_OK;
 }
 
-int lbm_ec_batch_set_tuning(lbm_ec_batch_t* B, int32_t fft_threads, int32_t collide_bx, int32_t collide_by) {
+int lbm_ec_batch_set_tuning(lbm_ec_batch_t* B, int32_t fft_threads, int32_t collide_bx, int32_t collide_by,
+                            int32_t collide_tw) {
   if (!B) return fail(LBM_EC_EINVAL, "NULL argument");
-  int rc = check_tuning(fft_threads, collide_bx, collide_by);
+  int rc = check_tuning(fft_threads, collide_bx, collide_by, collide_tw);
   if (rc) return rc;
   B->tu.fft_threads = fft_threads;
   B->tu.cbx = collide_bx;
   B->tu.cby = collide_by;
+  B->tu.ctw = collide_tw;
   B->dirty = true;
   return LBM_EC_OK;
 }

@@ -65,6 +65,7 @@ struct Consts {
   int NC;      // number of y chunks, ceil(ny / kChunk)
   int KP;      // row pitch of the interface factor table (NC - 1 rounded up to 8)
   int TH;      // rows per collide tile (tile_rows(ny))
+  int TW;      // columns per collide tile (nx: whole rows; set per launch from the tuning, results do not depend on it)
   double wp, wm, wgp, wgm;  // TRT rates: fluid +/-, charge +/-
   double K;                 // ion mobility
   double eps;               // permittivity
@@ -99,7 +100,23 @@ constexpr int kScanMax = 64 * kScanPerLane;
 // Factors of the interface system per (m, k), in this order (table rf).
 enum ReducedFactor { RF_INV = 0, RF_IB, RF_A, RF_P, RF_Q, RF_C, RF_G, RF_COUNT };
 
+// Row bands of collide tiles (one edge row each way per band).
 __host__ __device__ inline int collide_tiles(const Consts& c) { return (c.ny + c.TH - 1) / c.TH; }
+// Column tiles per band, and blocks of one collide launch (band-major: the
+// column tiles of a band are consecutive blocks).
+__host__ __device__ inline int collide_xtiles(const Consts& c) { return (c.nx + c.TW - 1) / c.TW; }
+__host__ __device__ inline int collide_blocks(const Consts& c) { return collide_tiles(c) * collide_xtiles(c); }
+
+// Columns per collide tile: by default whole rows while their ten LDS rows
+// fit one workgroup (nx <= 4096 in FP32 storage, 2048 in FP64: measured
+// faster than narrower tiles, which collide two halo columns per row in a
+// second round), tiles of kTileW columns (with recomputed halo columns)
+// beyond; `req` > 0 asks for a width.
+constexpr int kTileW = 1024;
+__host__ __device__ inline int tile_width(int nx, int req, int tsize) {
+  if (req > 0) return nx <= req ? nx : req;
+  return 10 * (long long)nx * tsize <= 160 * 1024 ? nx : (nx <= kTileW ? nx : kTileW);
+}
 
 // Per-row tables in the storage type (index k * ny + j).
 enum RowTable {
@@ -171,6 +188,7 @@ struct SlotDesc {
 struct Tuning {
   int fft_threads = 256;
   int cbx = 256, cby = 1;
+  int ctw = 0;  // columns per collide tile (0: tile_width's default)
 };
 
 // Batched kernels; slot s owns the blocks [off[k][s], off[k][s+1]) of launch k.
@@ -241,7 +259,7 @@ size_t yspec_lds_bytes(int ny);
 
 // LDS bytes of a collide tile (ten rows of nx values of T).
 template <typename T>
-size_t collide_lds_bytes(int nx);
+size_t collide_lds_bytes(int tw, int nx);
 
 // LDS bytes of the x-transform kernels for plan pl on blocks of `threads`.
 template <typename T>

@@ -238,13 +238,20 @@ __device__ __forceinline__ void stockham_pass_ip(C2<T>* __restrict__ buf, int N,
 }
 
 // The same transform as fft_lds, in place in buffer a (requires
-// fft_in_place(pl, blockDim.x, F)).
+// fft_in_place(pl, blockDim.x, F)); passes p0 .. p1-1 only (p1 < 0: to the
+// end), the earlier ones done elsewhere.
 template <typename T, bool INV, int F>
-__device__ __forceinline__ C2<T>* fft_lds_ip(C2<T>* a, const FftPlan& pl, const C2<T>* __restrict__ tw) {
+__device__ __forceinline__ C2<T>* fft_lds_ip(C2<T>* a, const FftPlan& pl, const C2<T>* __restrict__ tw, int p0 = 0,
+                                             int p1 = -1) {
   const int N = pl.n;
   int Ns = 1;
   const C2<T>* twp = tw + N;
-  for (int p = 0; p < pl.nr; ++p) {
+  for (int p = 0; p < p0; ++p) {
+    twp += Ns * (pl.r[p] - 1);
+    Ns *= pl.r[p];
+  }
+  const int pe = p1 < 0 ? pl.nr : p1;
+  for (int p = p0; p < pe; ++p) {
     const int R = pl.r[p];
     switch (R) {
       case 2: stockham_pass_ip<T, INV, 2, (F + 1) / 2>(a, N, Ns, twp); break;
@@ -260,24 +267,30 @@ __device__ __forceinline__ C2<T>* fft_lds_ip(C2<T>* a, const FftPlan& pl, const 
   return a;
 }
 
-// In place: one buffer of n elements plus the 32-double reduction scratch of
-// k_forward.  Ping-pong: two buffers, the second one doubling as the scratch
-// (used before the transform starts).
+// Row-sum scratch of k_forward: two rows of one FP64 sum per 64-element
+// group (nx <= 8192).
+constexpr int kSumGroups = 128;
+// In place: one buffer of n elements plus the row-sum scratch.  Ping-pong:
+// two buffers, the second one doubling as the scratch (used before the
+// transform starts).
 template <typename T>
 size_t fft_lds_bytes(const FftPlan& pl, int threads) {
   const size_t one = (size_t)pl.n * sizeof(C2<T>);
-  if (fft_in_place(pl, threads)) return one + 32 * sizeof(double);
-  return one + (one > 32 * sizeof(double) ? one : 32 * sizeof(double));
+  const size_t red = 2 * kSumGroups * sizeof(double);
+  if (fft_in_place(pl, threads)) return one + red;
+  return one + (one > red ? one : red);
 }
 template size_t fft_lds_bytes<double>(const FftPlan&, int);
 template size_t fft_lds_bytes<float>(const FftPlan&, int);
 
+// Ten rows of tw values; six of them with a halo slot at each end when the
+// tile is narrower than the row.
 template <typename T>
-size_t collide_lds_bytes(int nx) {
-  return 10 * (size_t)nx * sizeof(T);
+size_t collide_lds_bytes(int tw, int nx) {
+  return (10 * (size_t)tw + (tw < nx ? 12 : 0)) * sizeof(T);
 }
-template size_t collide_lds_bytes<double>(int);
-template size_t collide_lds_bytes<float>(int);
+template size_t collide_lds_bytes<double>(int, int);
+template size_t collide_lds_bytes<float>(int, int);
 
 // ------------------------------------------------------------- reductions
 // The value of lane (lane xor O) of a wave, O in {1, 2, 4, 8, 16, 32},
@@ -454,40 +467,39 @@ __device__ __forceinline__ T charge_at(const Consts& c, const ChargeSrc<T>& q, i
   return v;
 }
 
-// FP64 sums of the real and the imaginary parts of a[0 .. n) in an order
-// that depends on n alone (so launch shapes never change results): nseg =
-// min(16, ceil(n / 64)) segments of ceil(n / nseg) elements, each summed by
-// one wave with lane l taking every 64th element of the segment, then the
-// segments in order.  `red` holds 32 doubles of LDS; thread 0 receives the
-// sums.  NSEG = 16 is the code for n >= 1024 (16 segments; fixed bounds),
-// NSEG = 0 the general one.
-template <typename T, int NSEG>
-__device__ __forceinline__ void row_sums_fixed_order(const C2<T>* __restrict__ a, int n, double* red, double& s0,
-                                                     double& s1) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int nseg = NSEG ? NSEG : min(16, (n + 63) / 64);
-  const int seg = (n + nseg - 1) / nseg;
-  for (int q = wave; q < nseg; q += nw) {
-    const int lo = q * seg, hi = min(lo + seg, n);
-    double p0 = 0.0, p1 = 0.0;
-    for (int x = lo + lane; x < hi; x += 64) {
-      p0 += (double)a[x].re;
-      p1 += (double)a[x].im;
-    }
-    p0 = wave_sum(p0);
-    p1 = wave_sum(p1);
-    if (lane == 0) {
-      red[q] = p0;
-      red[16 + q] = p1;
-    }
+// FP64 row sums of the charge deviation in an order fixed by nx alone (so
+// launch shapes never change results), shaped like the first transform pass
+// (radix R0 = the plan's first radix, stride n / R0): the partial P(t) =
+// sum_r a[t + r n / R0] in order of r for t < n / R0; the partials of each
+// aligned group of 64 (t = 64 g + l) summed across the lanes of one wave by
+// the butterfly of wave_sum; the groups g = l, l + 64 in order by lane l of
+// one wave, then again by wave_sum.  Every path below gives each wave whole
+// aligned groups of t (blockDim is a multiple of 64).
+// group_sums: lane 0 of the wave stores the group sums of a row pair.
+__device__ __forceinline__ void group_sums(double v0, double v1, int g, double* red) {
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  if ((threadIdx.x & 63) == 0) {
+    red[g] = v0;
+    red[kSumGroups + g] = v1;
   }
-  __syncthreads();
-  s0 = 0.0;
-  s1 = 0.0;
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < nseg; ++q) {
-      s0 += red[q];
-      s1 += red[16 + q];
+}
+
+// After a barrier that follows group_sums: wave 0 combines the G groups,
+// thread 0 stores the row sums.
+__device__ __forceinline__ void combine_groups(const double* red, int G, double* __restrict__ dcsum, int j0,
+                                               bool has1) {
+  if (threadIdx.x < 64) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int g = threadIdx.x; g < G; g += 64) {
+      s0 += red[g];
+      s1 += red[kSumGroups + g];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (threadIdx.x == 0) {
+      dcsum[j0] = s0;
+      if (has1) dcsum[j0 + 1] = s1;
     }
   }
 }
@@ -497,6 +509,51 @@ __device__ __forceinline__ void row_sums_fixed_order(const C2<T>* __restrict__ a
 // imaginary parts of one complex transform.  Writes the source spectrum
 // s_m = -DFT(rho_c - r)_m / eps for m = 1 .. nx/2 (Eq. 4, 19) and the FP64
 // row sums of the charge deviation (the m = 0 mode).
+//
+// When each thread holds exactly NB radix-8 butterflies of the first pass
+// (nx = 8 NB blockDim, in place), the loaded values go through that pass in
+// registers (thread t loads x = t + blockDim i, i = q + 8 NB r for butterfly q
+// and input r: the stride-nx/8 inputs of the first Stockham pass), which
+// saves a round trip through LDS and a barrier; the arithmetic is that of the
+// LDS pass.
+template <typename T, int MODE, int NB>
+__device__ __forceinline__ void forward_first_pass(const Consts& c, const ChargeSrc<T>& q, const C2<T>* __restrict__ tw,
+                                                   C2<T>* __restrict__ a, double* red, int j0, int j1c, bool has1) {
+  constexpr int R = 8;
+  const int B = blockDim.x, t = threadIdx.x, wbase = t & ~63;
+  const int N = c.nx;
+  C2<T> v[NB][R];
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int x = t + B * (qq + NB * r);
+      v[qq][r] = C2<T>{charge_at<T, MODE>(c, q, x, j0), charge_at<T, MODE>(c, q, x, j1c)};
+    }
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!has1) v[qq][r].im = T(0);
+      s0 += (double)v[qq][r].re;
+      s1 += (double)v[qq][r].im;
+    }
+    group_sums(s0, s1, (wbase + B * qq) >> 6, red);
+  }
+  // first pass: Ns = 1, so k = 0 and the butterfly of t' = t + B q writes 8 t' + r
+  const C2<T>* twp = tw + N;
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[qq][r] = cmul(v[qq][r], twp[r - 1]);
+    dft8<T, false>(v[qq]);
+    const int tp = t + B * qq;
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[R * tp + r] = v[qq][r];
+  }
+}
+
 template <typename T, int MODE, int F>
 __device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>& q, const FftPlan& pl,
                                              const C2<T>* __restrict__ tw, C2<T>* __restrict__ spec,
@@ -504,42 +561,59 @@ __device__ __forceinline__ void forward_body(const Consts& c, const ChargeSrc<T>
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* a = reinterpret_cast<C2<T>*>(smem);
   C2<T>* b = a + pl.n;  // second transform buffer, or only the scratch when in place
-  double* red = reinterpret_cast<double*>(b);  // idle until the transform
+  double* red = reinterpret_cast<double*>(b);  // row-sum groups (idle until the transform)
   const bool ip = fft_in_place(pl, blockDim.x, F);
   const int j0 = 2 * bx, j1 = j0 + 1;
   const bool has1 = j1 < c.ny;
   const int j1c = has1 ? j1 : j0;  // a missing second row re-reads the first; dropped below
-  // U columns per thread per round: every load of a round is issued before
-  // the first sum (the column index is clamped, the stores are guarded)
-  constexpr int U = 4;
-  for (int x0 = threadIdx.x; x0 < c.nx; x0 += U * blockDim.x) {
-    T v0[U], v1[U];
+  const int R0 = pl.nr > 0 ? pl.r[0] : 1;
+  const int S = pl.n / R0;  // partials of the row sums
+  const int G = (S + 63) >> 6;
+  const int B = blockDim.x;
+  int p0 = 0;
+  if (ip && pl.r[0] == 8 && c.nx == 8 * B) {
+    forward_first_pass<T, MODE, 1>(c, q, tw, a, red, j0, j1c, has1);
+    p0 = 1;
+  } else if (F >= 16 && ip && pl.r[0] == 8 && c.nx == 16 * B) {
+    forward_first_pass<T, MODE, (F >= 16 ? 2 : 1)>(c, q, tw, a, red, j0, j1c, has1);
+    p0 = 1;
+  } else {
+    // U columns per thread per round: every load of a round is issued before
+    // the first sum (the column index is clamped, the stores are guarded);
+    // the rounds are uniform over a wave (its lanes hold one aligned group)
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    for (int xb = threadIdx.x - lane; xb < c.nx; xb += U * B) {
+      T v0[U], v1[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int x = min(x0 + u * (int)blockDim.x, c.nx - 1);
-      v0[u] = charge_at<T, MODE>(c, q, x, j0);
-      v1[u] = charge_at<T, MODE>(c, q, x, j1c);
-    }
+      for (int u = 0; u < U; ++u) {
+        const int x = min(xb + lane + u * B, c.nx - 1);
+        v0[u] = charge_at<T, MODE>(c, q, x, j0);
+        v1[u] = charge_at<T, MODE>(c, q, x, j1c);
+      }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int x = x0 + u * (int)blockDim.x;
-      if (x < c.nx) {
-        a[x] = C2<T>{v0[u], has1 ? v1[u] : T(0)};
+      for (int u = 0; u < U; ++u) {
+        const int x = xb + lane + u * B;
+        if (x < c.nx) a[x] = C2<T>{v0[u], has1 ? v1[u] : T(0)};
       }
     }
+    __syncthreads();
+    for (int tb = threadIdx.x - lane; tb < S; tb += B) {
+      const int t = tb + lane;
+      double s0 = 0.0, s1 = 0.0;
+      if (t < S)
+        for (int r = 0; r < R0; ++r) {
+          const C2<T> z = a[t + r * S];
+          s0 += (double)z.re;
+          s1 += (double)z.im;
+        }
+      group_sums(s0, s1, tb >> 6, red);
+    }
   }
   __syncthreads();
-  double s0, s1;
-  if (c.nx >= 1024)
-    row_sums_fixed_order<T, 16>(a, c.nx, red, s0, s1);
-  else
-    row_sums_fixed_order<T, 0>(a, c.nx, red, s0, s1);
-  if (threadIdx.x == 0) {
-    dcsum[j0] = s0;
-    if (has1) dcsum[j1] = s1;
-  }
-  __syncthreads();
-  C2<T>* z = ip ? fft_lds_ip<T, false, F>(a, pl, tw) : fft_lds<T, false>(a, b, pl, tw);
+  combine_groups(red, G, dcsum, j0, has1);
+  if (!ip) __syncthreads();  // the ping-pong transform overwrites the group sums
+  C2<T>* z = ip ? fft_lds_ip<T, false, F>(a, pl, tw, p0) : fft_lds<T, false>(a, b, pl, tw);
   const T sc = T(-0.5 / c.eps);
   const int N = pl.n;
   for (int m = threadIdx.x; m < c.M; m += blockDim.x) {
@@ -580,51 +654,45 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Transf
 //   D(-1) = (phi_upper - phi_lower)/ny - (S(ny-1) + 2 sum_{k<ny-1} S(k)) / (2 ny)
 //   phi_mean(j) = phi_lower + D(-1)/2 + sum_{k<j} D(k),  E_y mean = -(D(j) + D(j-1))/2
 // One block; FP64 throughout.
-// Exclusive prefix sum of v over the threads of the block in thread order
-// (blockDim.x a multiple of 64): a shuffle scan inside each wave, then the
-// wave totals in order.  `red` holds 16 doubles of LDS; `total` receives the
-// sum over the block.
-__device__ double block_exclusive_scan(double v, double* red, double& total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double x = v;
+// The column is swept in chunks of kMeanRows * 64 rows, one wave per chunk
+// (each lane holds kMeanRows consecutive rows in registers); the block takes
+// its waves' chunks in rounds.  Running sums: inclusive shuffle scans of the
+// lane partials inside a chunk, and the chunk totals added strictly in chunk
+// order, so every sum has an order fixed by ny alone (launch shapes never
+// change results).  A first sweep finds S(ny-1) and the sum of S, hence
+// D(-1); the second one writes the rows.  Both sweeps form S(j) by the same
+// operations, so they agree exactly.  Two rows per lane keep the inverse
+// transform kernel, which runs this as its block 0, within its 64 registers
+// without spills.
+constexpr int kMeanRows = 2;
+
+// Inclusive scan over the lanes of a wave (in lane order, Hillis-Steele).
+__device__ __forceinline__ double wave_incl_scan(double x) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const double y = __shfl_up(x, d, 64);
     if (lane >= d) x += y;
   }
-  __syncthreads();
-  if (lane == 63) red[wave] = x;
-  __syncthreads();
-  double before = 0.0, all = 0.0;
-  for (int w = 0; w < nw; ++w) {
-    const double t = red[w];
-    if (w < wave) before += t;
-    all += t;
-  }
-  total = all;
-  return before + (x - v);
+  return x;
 }
-
-// The column is swept in tiles of kMeanRows * blockDim.x rows; in a tile each
-// thread holds kMeanRows consecutive rows in registers (their loads all in
-// flight at once) and the running sums come from block scans of the thread
-// partials plus the carry of the earlier tiles.  A first sweep finds S(ny-1)
-// and the sum of S, hence D(-1); the second one writes the rows.  Both
-// sweeps form S(j) by the same operations, so they agree exactly.
-constexpr int kMeanRows = 8;
 
 __device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restrict__ rowsd,
                                                double* __restrict__ dmean) {
-  __shared__ double red[32];
+  __shared__ double tot[16], aux[16];
   const int ny = c.ny;
-  const int TB = kMeanRows * blockDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  constexpr int CR = 64 * kMeanRows;
+  const int nchunks = (ny + CR - 1) / CR;
   const double* r = rowsd + ROWD_R * ny;
   const double* dcs = rowsd + ROWD_DCSUM * ny;
   const double inx = (double)c.nx;
   // sbar(j) = -(r(j) + dcsum(j) / nx) / eps; S(j) = sum_{k <= j} sbar(k)
-  double carry = 0.0, tsum = 0.0;  // S before the tile; this thread's part of sum_{k < ny-1} S(k)
-  for (int t0 = 0; t0 < ny; t0 += TB) {
-    const int lo = t0 + (int)threadIdx.x * kMeanRows;
+  double carry = 0.0;  // S before the round's first chunk
+  double Ttot = 0.0;   // sum_{k < ny-1} S(k), chunk by chunk
+  for (int c0 = 0; c0 < nchunks; c0 += nw) {
+    const int ch = c0 + wave;
+    const int lo = ch * CR + lane * kMeanRows;
     double sb[kMeanRows];
     double part = 0.0;
 #pragma unroll
@@ -634,18 +702,29 @@ __device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restri
       sb[q] = lo + q < ny ? v : 0.0;
       part += sb[q];
     }
-    double tile;
-    double S = carry + block_exclusive_scan(part, red, tile);
+    const double x = wave_incl_scan(part);
+    const double xu = __shfl_up(x, 1, 64);  // every lane takes part in the shuffle
+    const double ex = lane ? xu : 0.0;
+    if (lane == 63) tot[wave] = ch < nchunks ? x : 0.0;
+    __syncthreads();
+    double cc = carry;  // S before this chunk
+    for (int w = 0; w < wave; ++w) cc += tot[w];
+    double S = cc + ex, ts = 0.0;
 #pragma unroll
     for (int q = 0; q < kMeanRows; ++q) {
       S += sb[q];
-      if (lo + q < ny - 1) tsum += S;
+      if (lo + q < ny - 1) ts += S;
     }
-    carry += tile;
+    ts = wave_sum(ts);
+    if (lane == 0) aux[wave] = ch < nchunks ? ts : 0.0;
+    __syncthreads();
+    for (int w = 0; w < nw && c0 + w < nchunks; ++w) {
+      carry += tot[w];
+      Ttot += aux[w];
+    }
     __syncthreads();
   }
   const double Slast = carry;
-  const double Ttot = block_sum(tsum, red + 16);
   const double dlow = (0.0 - 1.0) / (double)ny - (Slast + 2.0 * Ttot) / (2.0 * ny);
   const double phi0 = 1.0 + 0.5 * dlow;
   double* eym = rowsd + ROWD_EYM * ny;
@@ -654,9 +733,10 @@ __device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restri
   if (threadIdx.x == 0) dmean[0] = dlow;
   // D(j) = D(-1) + S(j); the potential is the exclusive running sum of D
   carry = 0.0;
-  double pcarry = 0.0;  // sum of D before the tile
-  for (int t0 = 0; t0 < ny; t0 += TB) {
-    const int lo = t0 + (int)threadIdx.x * kMeanRows;
+  double pcarry = 0.0;  // sum of D before the round's first chunk
+  for (int c0 = 0; c0 < nchunks; c0 += nw) {
+    const int ch = c0 + wave;
+    const int lo = ch * CR + lane * kMeanRows;
     double sb[kMeanRows], rr[kMeanRows];
     double part = 0.0;
 #pragma unroll
@@ -667,8 +747,14 @@ __device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restri
       sb[q] = lo + q < ny ? v : 0.0;
       part += sb[q];
     }
-    double tile;
-    const double off = carry + block_exclusive_scan(part, red, tile);
+    const double x = wave_incl_scan(part);
+    const double xu = __shfl_up(x, 1, 64);  // every lane takes part in the shuffle
+    const double ex = lane ? xu : 0.0;
+    if (lane == 63) tot[wave] = ch < nchunks ? x : 0.0;
+    __syncthreads();
+    double cc = carry;
+    for (int w = 0; w < wave; ++w) cc += tot[w];
+    const double off = cc + ex;
     double S = off, D[kMeanRows], pd = 0.0;
 #pragma unroll
     for (int q = 0; q < kMeanRows; ++q) {
@@ -676,9 +762,14 @@ __device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restri
       D[q] = dlow + S;
       if (lo + q < ny) pd += D[q];
     }
+    const double px = wave_incl_scan(pd);
+    const double pxu = __shfl_up(px, 1, 64);
+    const double pex = lane ? pxu : 0.0;
+    if (lane == 63) aux[wave] = ch < nchunks ? px : 0.0;
     __syncthreads();
-    double ptile;
-    double run = pcarry + block_exclusive_scan(pd, red, ptile);
+    double pc = pcarry;
+    for (int w = 0; w < wave; ++w) pc += aux[w];
+    double run = pc + pex;
     double Dprev = dlow + off;  // D(lo - 1); D(-1) = dlow
 #pragma unroll
     for (int q = 0; q < kMeanRows; ++q) {
@@ -693,8 +784,10 @@ __device__ __forceinline__ void mean_mode_body(const Consts& c, double* __restri
         Dprev = D[q];
       }
     }
-    carry += tile;
-    pcarry += ptile;
+    for (int w = 0; w < nw && c0 + w < nchunks; ++w) {
+      carry += tot[w];
+      pcarry += aux[w];
+    }
     __syncthreads();
   }
 }
@@ -976,11 +1069,16 @@ __device__ __forceinline__ void tri_scan_body(const Consts& c, const T* __restri
   }
 }
 
-// Four wavenumbers per 256-thread block.
+// Four wavenumbers per 256-thread block.  Each wave reads one wavenumber's
+// column of the chunk ends (one element per interface row), so the blocks
+// take their wavenumbers in the XCD-aware order (see xcd_order): the blocks
+// that share the cache lines of neighbouring wavenumbers sit on one XCD and
+// meet in its L2.
+__device__ __forceinline__ int xcd_order(int b, int G);
 template <typename T>
 __global__ void __launch_bounds__(256) k_tri_scan(Consts c, const T* __restrict__ rf, const C2<T>* __restrict__ ends,
                                                   C2<T>* __restrict__ iface) {
-  const int m = 1 + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int m = 1 + xcd_order(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (m >= c.M) return;
   tri_scan_body<T>(c, rf, ends, iface, m);
 }
@@ -1046,6 +1144,49 @@ __device__ __forceinline__ void inverse_gather(const Consts& c, const C2<T>* __r
   }
 }
 
+// Last pass (radix R, Ns = n / R) of an in-place inverse transform, its
+// outputs scaled by inv and stored as the real / imaginary parts to two
+// potential rows instead of to LDS (the same arithmetic as stockham_pass_ip).
+template <typename T, int R, int NB>
+__device__ __forceinline__ void inverse_last_pass(const C2<T>* __restrict__ buf, const FftPlan& pl,
+                                                  const C2<T>* __restrict__ tw, int last, T inv, T* __restrict__ phi0,
+                                                  T* __restrict__ phi1, bool has1) {
+  const int N = pl.n;
+  const int stride = N / R;
+  const C2<T>* twp = tw + N;
+  for (int p = 0, Ns = 1; p < last; ++p) {
+    twp += Ns * (pl.r[p] - 1);
+    Ns *= pl.r[p];
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int t = threadIdx.x + q * blockDim.x;
+    if (t < stride) {
+      // k = t % Ns = t, base = t
+      const C2<T>* tk = twp + t * (R - 1);
+      C2<T> v[R];
+      v[0] = buf[t];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C2<T> w = tk[r - 1];
+        w.im = -w.im;
+        v[r] = cmul(buf[t + r * stride], w);
+      }
+      if constexpr (R == 2) dft2<T, true>(v);
+      if constexpr (R == 3) dft3<T, true>(v);
+      if constexpr (R == 4) dft4<T, true>(v[0], v[1], v[2], v[3]);
+      if constexpr (R == 5) dft5<T, true>(v);
+      if constexpr (R == 8) dft8<T, true>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int x = t + r * stride;
+        phi0[x] = v[r].re * inv;
+        if (has1) phi1[x] = v[r].im * inv;
+      }
+    }
+  }
+}
+
 // --------------------------------------------------- inverse transform
 // Pair of rows per block: Z_m = X_m + i Y_m with the Hermitian halves of the
 // two solved spectra (m = 0 left out: it lives in the x-mean row), inverse
@@ -1072,11 +1213,27 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
   else
     inverse_gather<T, false, false>(c, spec, tt, iface, j0, has1, N, a);
   __syncthreads();
-  C2<T>* z = fft_in_place(pl, blockDim.x, F) ? fft_lds_ip<T, true, F>(a, pl, tw) : fft_lds<T, true>(a, b, pl, tw);
   const T inv = T(1.0 / (double)N);
+  T* phi0 = phi + (size_t)j0 * c.P;
+  T* phi1 = phi + (size_t)(has1 ? j1 : j0) * c.P;
+  if (fft_in_place(pl, blockDim.x, F) && pl.nr > 0) {
+    // all passes but the last in LDS; the last one stores straight to the
+    // potential rows (its butterfly t < n / R writes x = t + (n / R) r)
+    const int last = pl.nr - 1;
+    fft_lds_ip<T, true, F>(a, pl, tw, 0, last);
+    switch (pl.r[last]) {
+      case 2: inverse_last_pass<T, 2, (F + 1) / 2>(a, pl, tw, last, inv, phi0, phi1, has1); break;
+      case 3: inverse_last_pass<T, 3, (F + 2) / 3>(a, pl, tw, last, inv, phi0, phi1, has1); break;
+      case 4: inverse_last_pass<T, 4, (F + 3) / 4>(a, pl, tw, last, inv, phi0, phi1, has1); break;
+      case 5: inverse_last_pass<T, 5, (F + 4) / 5>(a, pl, tw, last, inv, phi0, phi1, has1); break;
+      default: inverse_last_pass<T, 8, (F + 7) / 8>(a, pl, tw, last, inv, phi0, phi1, has1); break;
+    }
+    return;
+  }
+  C2<T>* z = fft_in_place(pl, blockDim.x, F) ? a : fft_lds<T, true>(a, b, pl, tw);
   for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
-    phi[(size_t)j0 * c.P + x] = z[x].re * inv;
-    if (has1) phi[(size_t)j1 * c.P + x] = z[x].im * inv;
+    phi0[x] = z[x].re * inv;
+    if (has1) phi1[x] = z[x].im * inv;
   }
 }
 
@@ -1111,10 +1268,11 @@ __device__ __forceinline__ int xcd_order(int b, int G) {
 // Then the moments (Eq. 5-7), E = -grad phi (central differences, the mean
 // row in FP64), the equilibria (Eq. 10-11), the source (Eq. 12) and the TRT
 // collisions (Eq. 8-9, 13-15); writes the post-collision deviations.
-// mom == nullptr: no moments are emitted.
+// mom == nullptr: no moments are emitted.  STORE false: nothing is written
+// (a halo column of an x-tile, whose node belongs to the neighbouring tile).
 // gout receives the post-collision charge populations as stored (rounded
 // to T), for the charge density of the next step.
-template <typename T, typename C, bool PULL>
+template <typename T, typename C, bool PULL, bool STORE = true>
 __device__ __forceinline__ void collide_node(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
                                              T* __restrict__ Fout, T* __restrict__ Gout,
                                              const T* __restrict__ phi, const T* __restrict__ rows,
@@ -1194,9 +1352,11 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
   const size_t idx = row + x;
   // streaming stores: the populations are read again only next step
   auto put = [&](int i, C fv, C gv) {
-    __builtin_nontemporal_store((T)fv, &Fout[i * plane + idx]);
     gout[i] = (T)gv;
-    __builtin_nontemporal_store(gout[i], &Gout[i * plane + idx]);
+    if constexpr (STORE) {
+      __builtin_nontemporal_store((T)fv, &Fout[i * plane + idx]);
+      __builtin_nontemporal_store(gout[i], &Gout[i * plane + idx]);
+    }
   };
   {  // rest direction
     const C feq0 = w0 * drho - (w0 * rho) * uu15;
@@ -1233,25 +1393,31 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
   }
 }
 
-// One block per tile of whole rows [j0, j1): it collides the rows in order
-// and forms, from the post-collision charge populations it has just
-// written, the charge density the next step's pull will see, rho_c^{n+1}
-// (x, j) = sum_i g*_i(x - c_i, j - c_iy) with the electrode rules of
-// Table I and the re-reference constants of the deviations (k_q(j), one per
-// row).  Row r contributes
+// One block per tile of rows [j0, j1) and columns [x0, x0 + tw): it collides
+// the rows in order and forms, from the post-collision charge populations it
+// has just written, the charge density the next step's pull will see,
+// rho_c^{n+1}(x, j) = sum_i g*_i(x - c_i, j - c_iy) with the electrode rules
+// of Table I and the re-reference constants of the deviations (k_q(j), one
+// per row).  Row r contributes
 //   S(x) = g*_0(x) + g*_1(x-1) + g*_3(x+1)      to row r,
 //   U(x) = g*_2(x) + g*_5(x-1) + g*_6(x+1)      to row r+1,
 //   D(x) = g*_4(x) + g*_8(x-1) + g*_7(x+1)      to row r-1;
 // the injector row takes -(g*_4 + g*_7 + g*_8)(x) (anti-bounce-back, same
 // node) in place of U from below, the collector row takes its own D in place
-// of D from above.  The x neighbours come through LDS (whole rows, so x is
-// periodic inside the block); the y direction is marched.  Written: rq (the
-// density of rows j0 .. j1-1, without U from row j0-1 and without D from row
-// j1), eu[b] = U of row j1-1 and ed[b] = D of row j0 (the forward transform
-// adds them across the tile edges).  All sums in T, in a fixed order.
+// of D from above.  The x neighbours come through LDS; the y direction is
+// marched.  A tile of whole rows (tw = nx) wraps x inside the block; a
+// narrower tile also collides its two halo columns x0 - 1 and x0 + tw (the
+// neighbouring tiles' nodes, recomputed from the same inputs, so bit for bit
+// the values those tiles write) and keeps only their x movers.  Every node's
+// sum has the same expression in any tile width, so the width is free to
+// tune.  Written: rq (the density of rows j0 .. j1-1, without U from row
+// j0-1 and without D from row j1), eu[b] = U of row j1-1 and ed[b] = D of row
+// j0 (the forward transform adds them across the tile edges).  All sums in
+// T, in a fixed order.
 //
-// LDS: ten arrays of nx values of T: the six x movers of the current row,
-// own g*_4, the incomplete P of the current and of the previous row, U.
+// LDS: the six x movers of the current row (in a narrower tile with a halo
+// slot at each end), own g*_4, the incomplete P of the current and of the
+// previous row, U.
 // DENS: no collision; g* is read from Gin as stored (the density of a state
 // whose post-collision populations were changed in place).
 template <typename T, typename C, bool PULL, bool EMIT, bool DENS = false>
@@ -1259,55 +1425,78 @@ __device__ __forceinline__ void collide_tile(const Consts& c, const T* __restric
                                              T* __restrict__ Fout, T* __restrict__ Gout, const T* __restrict__ phi,
                                              const T* __restrict__ rows, const double* __restrict__ rowsd,
                                              double* __restrict__ mom, T* __restrict__ rq, T* __restrict__ eu,
-                                             T* __restrict__ ed, int b) {
+                                             T* __restrict__ ed, int blk) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nx = c.nx, ny = c.ny;
+  const int ntx = collide_xtiles(c);
+  const int b = blk / ntx;               // row band
+  const int x0 = (blk - b * ntx) * c.TW;  // first column
+  const int tw = min(c.TW, nx - x0);
+  const bool whole = tw == nx;
+  // mover slots: whole rows wrap inside the block; a narrower tile keeps
+  // column x0 - 1 + k in slot k
+  const int W = whole ? tw : tw + 2;
+  const int so = whole ? 0 : 1;  // slot of column x0 + xl is xl + so
   T* L = reinterpret_cast<T*>(smem);
   T* m1 = L;            // g*_1, g*_5, g*_8 move to x+1
-  T* m5 = L + nx;
-  T* m8 = L + 2 * nx;
-  T* m3 = L + 3 * nx;   // g*_3, g*_6, g*_7 move to x-1
-  T* m6 = L + 4 * nx;
-  T* m7 = L + 5 * nx;
-  T* o4 = L + 6 * nx;   // own g*_4
-  T* Pa = L + 7 * nx;   // P of rows r and r-1 (swapped every row)
-  T* Pb = L + 8 * nx;
-  T* Ua = L + 9 * nx;   // U of the previous row, then of the current one
+  T* m5 = L + W;
+  T* m8 = L + 2 * W;
+  T* m3 = L + 3 * W;    // g*_3, g*_6, g*_7 move to x-1
+  T* m6 = L + 4 * W;
+  T* m7 = L + 5 * W;
+  T* o4 = L + 6 * W;    // own g*_4
+  T* Pa = o4 + tw;      // P of rows r and r-1 (swapped every row)
+  T* Pb = Pa + tw;
+  T* Ua = Pb + tw;      // U of the previous row, then of the current one
   const int H = c.TH;
   const int j0 = b * H, j1 = min(j0 + H, ny);
   const T* kq = rows + ROW_KQ * ny;
+  const int slots = whole ? tw : tw + 2;
   for (int r = j0; r < j1; ++r) {
     T* Pcur = ((r - j0) & 1) ? Pb : Pa;   // P(r) being built
     T* Pprev = ((r - j0) & 1) ? Pa : Pb;  // P(r-1), complete
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+    for (int q = threadIdx.x; q < slots; q += blockDim.x) {
+      // q < tw: column x0 + q of the tile; then the halo columns x0 - 1, x0 + tw
+      const int xl = q < tw ? q : (q == tw ? -1 : tw);
+      int x = x0 + xl;
+      x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
       T gt[9];
-      if constexpr (DENS)
+      if constexpr (DENS) {
         local_pop<T>(c, Gin, x, r, gt);
-      else
-        collide_node<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, x, r, gt);
-      m1[x] = gt[1];
-      m5[x] = gt[5];
-      m8[x] = gt[8];
-      m3[x] = gt[3];
-      m6[x] = gt[6];
-      m7[x] = gt[7];
-      o4[x] = gt[4];
-      const T below = r == 0 ? -(gt[4] + gt[7] + gt[8]) : (r > j0 ? Ua[x] : T(0));
-      Pcur[x] = (below + gt[0]) + kq[r];
-      Ua[x] = gt[2];
+      } else {
+        if (q < tw)
+          collide_node<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, x, r, gt);
+        else
+          collide_node<T, C, PULL, false>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, nullptr, x, r, gt);
+      }
+      m1[xl + so] = gt[1];
+      m5[xl + so] = gt[5];
+      m8[xl + so] = gt[8];
+      m3[xl + so] = gt[3];
+      m6[xl + so] = gt[6];
+      m7[xl + so] = gt[7];
+      if (q < tw) {
+        o4[xl] = gt[4];
+        const T below = r == 0 ? -(gt[4] + gt[7] + gt[8]) : (r > j0 ? Ua[xl] : T(0));
+        Pcur[xl] = (below + gt[0]) + kq[r];
+        Ua[xl] = gt[2];
+      }
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-      const T D = (o4[x] + m8[xm]) + m7[xp];
+    for (int xl = threadIdx.x; xl < tw; xl += blockDim.x) {
+      const int x = x0 + xl;
+      // slots of the columns xl - 1 and xl + 1
+      const int sm = whole ? (xl == 0 ? tw - 1 : xl - 1) : xl;
+      const int sp = whole ? (xl == tw - 1 ? 0 : xl + 1) : xl + 2;
+      const T D = (o4[xl] + m8[sm]) + m7[sp];
       if (r > j0)
-        rq[(size_t)(r - 1) * c.P + x] = Pprev[x] + D;
+        rq[(size_t)(r - 1) * c.P + x] = Pprev[xl] + D;
       else if (r > 0)
         ed[(size_t)b * c.P + x] = D;
-      const T P = (Pcur[x] + m1[xm]) + m3[xp];
-      const T U = (Ua[x] + m5[xm]) + m6[xp];
-      Pcur[x] = P;
-      Ua[x] = U;
+      const T P = (Pcur[xl] + m1[sm]) + m3[sp];
+      const T U = (Ua[xl] + m5[sm]) + m6[sp];
+      Pcur[xl] = P;
+      Ua[xl] = U;
       if (r == j1 - 1) {
         rq[(size_t)r * c.P + x] = r == ny - 1 ? P + D : P;
         if (r < ny - 1) eu[(size_t)b * c.P + x] = U;
@@ -1839,7 +2028,7 @@ int batch_blocks(const Consts& c, int k) {
     case BK_TRI_REDUCED:
       if (nm <= 0 || c.NC < 2) return 0;
       return c.NC - 1 <= kScanMax ? (nm + 3) / 4 : (nm + 255) / 256;
-    case BK_COLLIDE: return collide_tiles(c);
+    case BK_COLLIDE: return collide_blocks(c);
     case BK_STATS: return 1;
   }
   return 0;
@@ -1956,10 +2145,12 @@ hipError_t launch_inverse(const Consts& c, const Bufs& b, const FftPlan& pl, con
 }
 
 template <typename T, typename C>
-hipError_t launch_collide(const Consts& c, const Bufs& b, bool pull, bool emit, int src, int dst,
+hipError_t launch_collide(const Consts& c0, const Bufs& b, bool pull, bool emit, int src, int dst,
                           const Tuning& tu, hipStream_t s) {
-  dim3 blk(tu.cbx * tu.cby), grd(collide_tiles(c));
-  const size_t lds = collide_lds_bytes<T>(c.nx);
+  Consts c = c0;
+  c.TW = tile_width(c.nx, tu.ctw, (int)sizeof(T));
+  dim3 blk(tu.cbx * tu.cby), grd(collide_blocks(c));
+  const size_t lds = collide_lds_bytes<T>(c.TW, c.nx);
   const T* Fin = (const T*)b.f[src];
   const T* Gin = (const T*)b.g[src];
   T* Fout = (T*)b.f[dst];
@@ -2034,8 +2225,10 @@ hipError_t launch_yspec(const Consts& c, const Bufs& b, const FftPlan& py, hipSt
 }
 
 template <typename T>
-hipError_t launch_density(const Consts& c, const Bufs& b, int cur, const Tuning& tu, hipStream_t s) {
-  hipLaunchKernelGGL(k_density<T>, dim3(collide_tiles(c)), dim3(tu.cbx * tu.cby), collide_lds_bytes<T>(c.nx), s, c,
+hipError_t launch_density(const Consts& c0, const Bufs& b, int cur, const Tuning& tu, hipStream_t s) {
+  Consts c = c0;
+  c.TW = tile_width(c.nx, tu.ctw, (int)sizeof(T));
+  hipLaunchKernelGGL(k_density<T>, dim3(collide_blocks(c)), dim3(tu.cbx * tu.cby), collide_lds_bytes<T>(c.TW, c.nx), s, c,
                      (const T*)b.g[cur], (const T*)b.rows, (T*)b.rq, (T*)b.eu, (T*)b.ed);
   return hipGetLastError();
 }

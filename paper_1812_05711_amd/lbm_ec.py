@@ -130,9 +130,9 @@ def lib():
     L.lbm_ec_batch_free_bytes.restype = ctypes.c_size_t
     L.lbm_ec_batch_destroy.argtypes = [vp]
     L.lbm_ec_batch_destroy.restype = None
-    L.lbm_ec_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.lbm_ec_set_tuning.argtypes = [vp, i32, i32, i32, i32]
     L.lbm_ec_set_tuning.restype = ctypes.c_int
-    L.lbm_ec_batch_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.lbm_ec_batch_set_tuning.argtypes = [vp, i32, i32, i32, i32]
     L.lbm_ec_batch_set_tuning.restype = ctypes.c_int
     L.lbm_ec_debug_poison.argtypes = [vp]
     L.lbm_ec_debug_poison.restype = ctypes.c_int
@@ -268,8 +268,9 @@ class Simulation:
                  "q_collector"]
         return dict(zip(names, list(buf))), code == OK
 
-    def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
-        _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+    def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1, collide_tw=0):
+        _check(lib().lbm_ec_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by),
+                                       int(collide_tw)))
 
     def set_y_solver(self, solver):
         """'tridiagonal' (default) or 'spectral' (lbm_ec_set_y_solver)."""
@@ -402,8 +403,9 @@ class Batch:
         _check(lib().lbm_ec_batch_history(self._h, int(slot), buf, self.hist_rows))
         return np.frombuffer(buf, dtype=np.float64).reshape(self.hist_rows, HIST_COLS).copy()
 
-    def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1):
-        _check(lib().lbm_ec_batch_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by)))
+    def set_tuning(self, fft_threads=256, collide_bx=256, collide_by=1, collide_tw=0):
+        _check(lib().lbm_ec_batch_set_tuning(self._h, int(fft_threads), int(collide_bx), int(collide_by),
+                                             int(collide_tw)))
 
     def set_T(self, slot, T):
         """Continue the slot at electric Rayleigh number T (lbm_ec_batch_set_T)."""

@@ -39,7 +39,7 @@ def test_defaults_and_validation(E):
     assert (p.nx, p.ny, p.T, p.C, p.M, p.Fe) == (122, 100, 200.0, 10.0, 10.0, 4000.0)
     assert E.lib().lbm_ec_validate(ctypes.byref(p)) == E.OK
     for bad in (dict(tau_plus=0.5), dict(ny=2), dict(Lambda=0.0), dict(Fe=-1.0), dict(init_mode=7),
-                dict(nx=5000, precision="fp64"), dict(charge_rates=3)):
+                dict(nx=8200, precision="fp32"), dict(nx=5122, precision="fp64"), dict(charge_rates=3)):
         kw = dict(nx=122, ny=100)
         kw.update(bad)
         q = E.make_params(**kw)
@@ -68,6 +68,13 @@ def test_create_rejects_small_workspace_without_touching_the_device(E):
     assert "workspace" in E.lib().lbm_ec_last_error().decode()
 
 
+def _five_smooth(n):
+    for q in (2, 3, 5):
+        while n % q == 0:
+            n //= q
+    return n == 1
+
+
 def _documented_verdict(d):
     """lbm_ec_validate's rules as include/lbm_ec.h states them, restated."""
     import math
@@ -75,7 +82,9 @@ def _documented_verdict(d):
     fin = math.isfinite
     if d["nx"] < 1 or d["ny"] < 3 or d["precision"] not in (0, 1, 2):
         return False
-    if d["nx"] > (2048 if d["precision"] == 0 else 4096) or d["nx"] * d["ny"] > 2**31:
+    if d["nx"] > 8192 or d["nx"] * d["ny"] > 2**31:
+        return False
+    if d["precision"] == 0 and d["nx"] > 5120 and not _five_smooth(d["nx"]):
         return False
     if not (d["tau_plus"] > 0.5 and fin(d["tau_plus"])):
         return False
@@ -109,7 +118,7 @@ def test_validation_follows_the_documented_rules(E):
 
     @hypothesis.settings(max_examples=400, deadline=None, derandomize=True)
     @hypothesis.given(
-        nx=st.one_of(st.integers(-2, 5000), st.sampled_from([1, 2048, 2049, 4096, 4097])),
+        nx=st.one_of(st.integers(-2, 9000), st.sampled_from([1, 2048, 4096, 5120, 5122, 5625, 8192, 8193])),
         ny=st.one_of(st.integers(-2, 600000), st.sampled_from([3, 2, 524288, 524289])),
         T=real(1e-3, 1e4), C=real(0.0, 1e3), M=real(1e-2, 1e3), Fe=real(1e-2, 1e6),
         tau_plus=real(0.3, 3.0), Lambda=real(1e-8, 10.0), Lambda_g=real(1e-8, 10.0),

@@ -82,11 +82,20 @@ def test_fp32_storage_small(nx, ny, steps, precision):
     _check(dict(BASE, nx=nx, ny=ny, precision=precision), steps, TOL32)
 
 
-@pytest.mark.parametrize("precision,nx", [("fp64", 2048), ("fp32_f64math", 4096), ("fp32", 4096)])
+@pytest.mark.parametrize("precision,nx", [("fp64", 4096), ("fp64", 8192), ("fp32_f64math", 8192), ("fp32", 8192),
+                                          ("fp64", 3000), ("fp32_f64math", 1500)])
 def test_widest_grid(precision, nx):
-    """The widest row each storage type allows (whole rows in one collide
-    tile's LDS; the longest x transform)."""
+    """Rows wider than one collide tile (1024 columns, halo columns
+    recomputed), up to the longest x transform a workgroup's LDS holds
+    (8192 points in either storage type), and ragged last tiles (3000 =
+    2 x 1024 + 952, 1500 = 1024 + 476)."""
     _check(dict(BASE, nx=nx, ny=12, precision=precision), 20, TOL64 if precision == "fp64" else TOL32)
+
+
+def test_widest_grid_fp64_tall():
+    """The 4096-wide row in FP64 over several tile bands (ny = 520: two-row
+    bands), so that tile edges in x and y meet."""
+    _check(dict(BASE, nx=4096, ny=520), 6, TOL64)
 
 
 def test_fp32_f64math_full_122x100_2000_steps():
@@ -126,13 +135,15 @@ def test_determinism_bitwise():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_f64math"])
 def test_launch_shapes_do_not_change_results(precision):
-    """Threads per transform block and per collide tile are free to tune:
-    the fields are bitwise the same (ny = 600 gives two-row collide tiles)."""
+    """Threads per transform block, threads per collide tile and columns per
+    collide tile are free to tune: the fields are bitwise the same (ny = 600
+    gives two-row collide tiles; widths 64 and 37 give x-tiles with halo
+    columns and a ragged last tile)."""
     from paper_1812_05711_amd.lbm_ec import Simulation
     import torch
 
     out = []
-    for tu in ((128, 64, 1), (512, 1024, 1), (256, 128, 2)):
+    for tu in ((128, 64, 1, 0), (512, 1024, 1, 0), (256, 128, 2, 0), (256, 64, 1, 64), (128, 128, 1, 37)):
         sim = Simulation(device="cuda:0", precision=precision, **dict(BASE, nx=100, ny=600))
         sim.set_tuning(*tu)
         sim.step(15)
@@ -141,4 +152,5 @@ def test_launch_shapes_do_not_change_results(precision):
         out.append({k: v.cpu().numpy() for k, v in f.items()})
         sim.close()
     for k in out[0]:
-        assert np.array_equal(out[0][k], out[1][k]) and np.array_equal(out[0][k], out[2][k]), k
+        for o in out[1:]:
+            assert np.array_equal(out[0][k], o[k]), k
