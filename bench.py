@@ -23,14 +23,20 @@ Prints one JSON line:
                  {64, 128, 256, 512} with weights 0.4 / 0.3 / 0.2 / 0.1, nx =
                  smallest 5-smooth >= round(1.22 ny), T uniform in [120, 400],
                  C in {1, 10, 100}, FP32 storage, 5000 steps per request,
-                 admission by workspace footprint; p50 / p99 latency from
-                 arrival to final fields (after the warm-up requests), runs/s
+                 admission by workspace footprint; 2000 requests of which the
+                 first 200 warm up; p50 / p99 latency from arrival to final
+                 fields, runs/s, longest admission queue
+  serve_admission_bound  the same stream on a 0.25 GB workspace, where
+                 admission by footprint binds (requests queue for memory)
   sweep          the batched T sweep: 64 instances, ny uniform in 64..256,
                  nx = smallest 5-smooth >= round(1.22 ny), T uniform in
                  [100, 250], C = 10, M = 10, FP32 storage, 20000 steps each,
                  autotuned launch shapes, one batch (captured HIP graphs),
                  against the same instances run one at a time through
-                 lbm_ec_step (timed over 1000 steps each, scaled to 20000)
+                 lbm_ec_step (timed over 1000 steps each, scaled to 20000);
+                 per instance the ionic times the run covers and the slope of
+                 ln A1 with its R^2, a growth rate only where the run covers
+                 at least one ionic time (a transient slope otherwise)
   hysteresis     Ne_0 = I / I_0 on both branches of section V.2 in one batch
                  on a 61 x 50 channel (C = 10, M = 10, Fe = 4000, FP32
                  storage): runs from rest at T = 155, 160, 165; one run whose
@@ -134,18 +140,30 @@ def sweep_section(steps, plain_steps):
     log(f"sweep: batched {r['seconds']:.2f} s; plain, {plain_steps} steps each")
     tp = sweep.run_plain(cfgs, plain_steps) * steps / plain_steps
     T = [c["T"] for c in cfgs]
-    g = r["growth"]
+    fits = r["fits"]
     order = np.argsort(T)
+    # a rate is reported as a number only where the run covers at least one
+    # ionic time; shorter runs give the early transient, reported with the fit
+    # quality but not as a growth rate
+    rates = []
+    for i in order:
+        f = fits[i]
+        rates.append({"T": round(T[i], 2), "ny": cfgs[i]["ny"], "ionic_times": round(f["span"], 3),
+                      "growth_rate": None if f["transient"] else round(f["rate"], 4),
+                      "transient_slope": round(f["rate"], 4) if f["transient"] else None,
+                      "fit_r2": round(f["r2"], 4)})
     return {"instances": len(cfgs), "steps": steps, "nodes": nodes,
             "batched_runs_per_s": len(cfgs) / r["seconds"], "plain_runs_per_s": len(cfgs) / tp,
             "speedup": tp / r["seconds"], "batched_seconds": r["seconds"], "plain_seconds": tp,
             "batched_mlups": nodes * steps / r["seconds"] / 1e6,
+            "us_per_step": r["seconds"] / steps * 1e6,
             "plain_sample": f"{plain_steps} steps per instance, scaled to {steps}",
             "tuning": list(r["tuning"]) if r["tuning"] else None,
-            "growth_rate_by_T": [[round(T[i], 2), round(g[i], 4)] for i in order]}
+            "instances_over_one_ionic_time": sum(1 for f in fits if not f["transient"]),
+            "growth_by_T": rates}
 
 
-def serve_section(n, warmup, budget_gb):
+def serve_section(n, warmup, budget_gb, tag="serve"):
     from paper_1812_05711_amd.serve import BatchBackend, make_requests, serve
 
     from paper_1812_05711_amd import autotune
@@ -153,13 +171,15 @@ def serve_section(n, warmup, budget_gb):
     reqs = make_requests(n, rate=50.0, steps=5000)
     # launch shapes tuned on a sample of the stream's mix (before the clock starts)
     tuning = autotune.tune_batch([r["params"] for r in reqs[:48]])
-    log(f"serve: {n} requests at 50/s, budget {budget_gb} GB, launch shapes {tuning}")
+    log(f"{tag}: {n} requests at 50/s, budget {budget_gb} GB, launch shapes {tuning}")
     be = BatchBackend(int(budget_gb * (1 << 30)), max_slots=512, tuning=tuning)
-    records, summary = serve(reqs, be, chunk=100, warmup=warmup, max_wall=600.0)
+    records, summary = serve(reqs, be, chunk=100, warmup=warmup, max_wall=900.0)
     be.close()
     summary.update({"rate_per_s": 50.0, "steps_per_request": 5000, "warmup_requests": warmup,
                     "budget_bytes": int(budget_gb * (1 << 30)), "chunk_steps": 100, "tuning": list(tuning)})
-    log(f"serve: p50 {summary['p50_s']:.3f} s, p99 {summary['p99_s']:.3f} s, {summary['runs_per_s']:.1f} runs/s")
+    summary["refused"] = len(summary["refused"])
+    log(f"{tag}: p50 {summary['p50_s']:.3f} s, p99 {summary['p99_s']:.3f} s, {summary['runs_per_s']:.1f} runs/s, "
+        f"longest queue {summary['max_queue']}")
     return summary
 
 
@@ -197,9 +217,12 @@ def main():
     ap.add_argument("--noise-amp", type=float, default=WORKLOAD["noise_amp"], help="relative charge noise")
     ap.add_argument("--y-solver", default="tridiagonal", choices=["tridiagonal", "spectral"],
                     help="y solve of the m >= 1 modes (spectral: the odd-extension route of Eq. 21-25)")
-    ap.add_argument("--serve-requests", type=int, default=600)
-    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-bound-budget-gb", type=float, default=0.25,
+                    help="budget of the second serve leg, small enough that admission by footprint binds "
+                         "(0: no second leg)")
     ap.add_argument("--sweep-steps", type=int, default=20000)
     ap.add_argument("--sweep-plain-steps", type=int, default=1000)
     args = ap.parse_args()
@@ -292,6 +315,9 @@ def main():
     out["sweep"] = None if args.no_sweep else sweep_section(args.sweep_steps, args.sweep_plain_steps)
     out["serve"] = None if args.no_serve else serve_section(args.serve_requests, args.serve_warmup,
                                                             args.serve_budget_gb)
+    out["serve_admission_bound"] = (None if args.no_serve or args.serve_bound_budget_gb <= 0 else
+                                    serve_section(args.serve_requests, args.serve_warmup,
+                                                  args.serve_bound_budget_gb, tag="serve (bound)"))
     out["hysteresis"] = None if args.no_hysteresis else hysteresis_section()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nx, ny)

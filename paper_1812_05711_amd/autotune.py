@@ -1,5 +1,7 @@
 """Autotuner for the launch shapes of the time step (they never change
-results): threads per x-transform block and per collide tile.
+results): threads per x-transform block, threads per collide tile and, for
+rows wider than 512, columns per collide tile (whole rows or tiles of 1024 or
+512 columns that recompute their halo columns).
 
 Candidates are timed with events on the batch's stream, on a throwaway batch
 of the same composition (so the real run is not advanced), and the best is
@@ -12,6 +14,7 @@ import os
 
 FFT_THREADS = (64, 128, 256, 512)
 COLLIDE_SHAPES = ((64, 1), (128, 1), (256, 1), (512, 1), (1024, 1))
+TILE_WIDTHS = (0, 1024, 512)  # 0: the library's default width
 DEFAULT = (256, 256, 1)
 
 
@@ -73,7 +76,10 @@ def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
     best_fft, best_t = DEFAULT[0], float("inf")
     for ft in FFT_THREADS:
         b.set_tuning(ft, DEFAULT[1], DEFAULT[2])
-        t = _time_batch(b, steps)
+        try:
+            t = _time_batch(b, steps)
+        except Exception:  # a transform block too small for the widest slot
+            continue
         if t < best_t:
             best_fft, best_t = ft, t
     best_shape, best_t = DEFAULT[1:], float("inf")
@@ -91,13 +97,21 @@ def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
 
 
 def tune_single(sim, steps=16):
-    """Best launch shapes for one simulation (advances it by the timing steps)."""
+    """Best launch shapes (fft_threads, collide_bx, collide_by, collide_tw)
+    for one simulation (advances it by the timing steps).  Shapes the library
+    refuses (a transform block too small for the row) are skipped."""
     import torch
 
-    best, best_t = DEFAULT, float("inf")
+    from .lbm_ec import LbmEcError
+
+    widths = [w for w in TILE_WIDTHS if w == 0 or w < sim.nx]
+    best, best_t = DEFAULT + (0,), float("inf")
     for ft in FFT_THREADS:
-        for bx, by in COLLIDE_SHAPES:
-            sim.set_tuning(ft, bx, by)
+        for (bx, by), tw in [(s, w) for s in COLLIDE_SHAPES for w in widths]:
+            try:
+                sim.set_tuning(ft, bx, by, tw)
+            except LbmEcError:
+                continue
             sim.step(2)
             start = torch.cuda.Event(enable_timing=True)
             end = torch.cuda.Event(enable_timing=True)
@@ -107,6 +121,6 @@ def tune_single(sim, steps=16):
             end.synchronize()
             t = start.elapsed_time(end) / steps
             if t < best_t:
-                best, best_t = (ft, bx, by), t
+                best, best_t = (ft, bx, by, tw), t
     sim.set_tuning(*best)
     return best, best_t

@@ -1239,7 +1239,11 @@ __device__ __forceinline__ void inverse_body(const Consts& c, const C2<T>* __res
 
 // Block 0 solves the x-mean mode (needed only by the collision, and
 // independent of the m >= 1 modes, so it runs beside the transforms);
-// blocks 1.. are the row pairs.
+// blocks 1.. are the row pairs, taken in the XCD-aware order (see
+// xcd_order), so that the sixteen row pairs of a 32-row chunk, which read the
+// same interface values and chunk responses, sit on one XCD and share them
+// in its L2.
+__device__ __forceinline__ int xcd_order(int b, int G);
 template <typename T, int F>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TransformWaves<T, F>::value))) k_inverse(Consts c, const C2<T>* __restrict__ spec, const T* __restrict__ tt,
                                                  const C2<T>* __restrict__ iface, FftPlan pl,
@@ -1249,7 +1253,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Transf
     mean_mode_body(c, rowsd, dmean);
     return;
   }
-  inverse_body<T, F>(c, spec, tt, iface, pl, tw, phi, blockIdx.x - 1);
+  inverse_body<T, F>(c, spec, tt, iface, pl, tw, phi, xcd_order(blockIdx.x - 1, gridDim.x - 1));
 }
 
 // Workgroups are dealt to the eight XCDs in turn; block b takes index

@@ -19,7 +19,7 @@ import time
 
 import numpy as np
 
-from .sweep import five_smooth_at_least
+from .workloads import five_smooth_at_least
 
 SIZES = (64, 128, 256, 512)
 SIZE_WEIGHTS = (0.4, 0.3, 0.2, 0.1)

@@ -18,32 +18,7 @@ import numpy as np
 
 from . import autotune
 from .lbm_ec import Batch, Simulation, batch_workspace_bytes, make_params
-
-
-def five_smooth_at_least(n: int) -> int:
-    m = max(1, int(n))
-    while True:
-        k = m
-        for p in (2, 3, 5):
-            while k % p == 0:
-                k //= p
-        if k == 1:
-            return m
-        m += 1
-
-
-def sweep_configs(n=64, seed=181205711, ny_range=(64, 256), T_range=(100.0, 250.0), C=10.0, M=10.0, Fe=4000.0,
-                  tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6, noise_amp=1e-3, precision="fp32_f64math"):
-    """The seeded instance list of a sweep (dicts for make_params)."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for i in range(n):
-        ny = int(rng.integers(ny_range[0], ny_range[1] + 1))
-        nx = five_smooth_at_least(round(1.22 * ny))
-        T = float(rng.uniform(*T_range))
-        out.append(dict(nx=nx, ny=ny, T=T, C=C, M=M, Fe=Fe, tau_plus=tau_plus, Lambda=Lambda, Lambda_g=Lambda_g,
-                        noise_amp=noise_amp, seed=seed, instance_id=i, precision=precision))
-    return out
+from .workloads import five_smooth_at_least, sweep_configs  # noqa: F401 (the sweep's instance list)
 
 
 def ionic_time(cfg):
@@ -55,14 +30,29 @@ def ionic_time(cfg):
 def growth_rate(history, t0, col=4):
     """Slope of ln(history[:, col]) versus t / t0 over the second half of the
     rows (col 4: the first x mode of u_y)."""
+    return growth_fit(history, t0, col)["rate"]
+
+
+def growth_fit(history, t0, col=4):
+    """The growth-rate fit of growth_rate with its quality: rate (per ionic
+    time), r2 (coefficient of determination of the straight line through
+    ln A over the fitted half), span (ionic times the whole run covers) and
+    transient (True when the run covers less than one ionic time, so that
+    the rate describes the early transient rather than the linear growth or
+    decay that locates T_c)."""
     rows = history[history[:, 0] > 0]
     if len(rows) < 4:
-        return float("nan")
+        return dict(rate=float("nan"), r2=float("nan"), span=0.0, transient=True)
     rows = rows[np.argsort(rows[:, 0])]
     h = len(rows) // 2
     t = rows[h:, 0] / t0
     a = np.log(np.maximum(rows[h:, col], 1e-300))
-    return float(np.polyfit(t, a, 1)[0])
+    p = np.polyfit(t, a, 1)
+    res = a - np.polyval(p, t)
+    ss = float(np.sum((a - a.mean()) ** 2))
+    r2 = 1.0 - float(np.sum(res ** 2)) / ss if ss > 0 else 1.0
+    span = float(rows[-1, 0] / t0)
+    return dict(rate=float(p[0]), r2=r2, span=span, transient=span < 1.0)
 
 
 def make_batch(configs, steps, emit_every=100, device="cuda:0", tuning=None):
@@ -102,9 +92,9 @@ def run_batched(configs, steps, emit_every=100, device="cuda:0", tune=True, prog
     dt = time.perf_counter() - t
     done = b.poll()
     assert sorted(done) == sorted(slots)
-    rates = [growth_rate(b.history(s), ionic_time(c)) for s, c in zip(slots, configs)]
+    fits = [growth_fit(b.history(s), ionic_time(c)) for s, c in zip(slots, configs)]
     b.close()
-    return dict(seconds=dt, growth=rates, tuning=tuning)
+    return dict(seconds=dt, growth=[f["rate"] for f in fits], fits=fits, tuning=tuning)
 
 
 def run_plain(configs, steps, device="cuda:0"):

@@ -81,3 +81,21 @@ def test_threshold_zero_crossing():
     assert sweep.zero_crossing([160.0, 162.0], [-0.2, -0.1]) is None
     cfgs = sweep.threshold_configs(122, 100, [160.0, 165.0])
     assert [c["T"] for c in cfgs] == [160.0, 165.0] and all(c["init_mode"] == "eq29" for c in cfgs)
+
+
+def test_growth_fit_quality_and_transient_flag():
+    from paper_1812_05711_amd.sweep import growth_fit
+
+    t0 = 1000.0
+    steps = np.arange(1, 41) * 50.0  # 2 ionic times
+    hist = np.zeros((40, 7))
+    hist[:, 0] = steps
+    hist[:, 4] = 3e-4 * np.exp(-0.4 * steps / t0)
+    f = growth_fit(hist, t0)
+    assert abs(f["rate"] + 0.4) < 1e-9 and abs(f["r2"] - 1.0) < 1e-12
+    assert f["span"] == 2.0 and not f["transient"]
+    short = growth_fit(hist, 4 * t0)  # the same rows cover half an ionic time
+    assert short["transient"] and short["span"] == 0.5
+    rng = np.random.default_rng(1)
+    hist[:, 4] = np.exp(rng.standard_normal(40))
+    assert growth_fit(hist, t0)["r2"] < 0.5

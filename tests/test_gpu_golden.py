@@ -11,8 +11,8 @@ hydrostatic density departure is held to the same relative tolerance), u as
 a vector field, rho_c and phi.  FP64 storage must match to 1e-11 and
 FP32-deviation storage to 1e-5 on every field.  FP32-deviation storage with
 FP32 collision arithmetic meets 1e-5 on rho, rho - 1, rho_c and phi; its
-velocity at 1e-5 is an expected failure (the precision notes of the design
-document give the measured level and its cause)."""
+velocity is held only to a regression bound (the precision notes of the
+design document give the measured level and the experiments on its cause)."""
 
 import os
 
@@ -89,13 +89,18 @@ def test_cfg1_against_oracle(precision, tol):
     _gate(gold, res, snaps, precision, tol, gate_u=precision != "fp32")
 
 
-@pytest.mark.xfail(reason="FP32 collision arithmetic: velocity error above 1e-5 after 10000 steps", strict=False)
-def test_cfg1_fp32_arithmetic_velocity():
+def test_cfg1_fp32_arithmetic_velocity_regression_bound():
+    """Not a parity test: FP32 storage with FP32 collision arithmetic misses
+    the 1e-5 gate on u (1.4e-4 of max |u| after 10000 steps; the design notes
+    give the experiments that place the error in the fluid collision's FP32
+    arithmetic as a whole).  FP32 storage meets the gate with FP64 collision
+    arithmetic (test_cfg1_against_oracle[fp32_f64math]).  This bound, twice the
+    measured level, only catches a regression of the FP32-arithmetic mode."""
     gold = _golden(GOLDEN, "1024 x 840", "cfg1")
     snaps = _snapshots(gold)
     res = _run("fp32", snaps, KW)
-    e = _gate(gold, res, snaps, "fp32", 1e-5, gate_u=True)
-    assert e["u"] <= 1e-5
+    e = _gate(gold, res, snaps, "fp32", 1e-5, gate_u=False)
+    assert e["u"] <= 3e-4, e
 
 
 def _cfg2(step):
