@@ -1258,7 +1258,9 @@ int lbm_ec_profile_end(lbm_ec_t* h, double* ms, int64_t* launches, int32_t n) {
 // [phi][rows FP64][D][moments], each region 256-byte aligned: the
 // post-collision populations with the charge density the collide tiles
 // summed from them, and everything lbm_ec_fields reads, so a loaded
-// instance continues bit for bit.
+// instance continues bit for bit.  Version 4: the charge populations' x
+// movers are stored shifted by their c_ix (version 3 stored them at their
+// node), so older checkpoints are refused.
 namespace {
 constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'E', 'C', 'C', 'K', '1'};
 struct CkptHeader {
@@ -1309,7 +1311,7 @@ CkptLayout ckpt_layout(const lbm_ec* h) {
 void ckpt_fill(const lbm_ec* h, CkptHeader* H, uint64_t total) {
   std::memset(H, 0, sizeof(*H));
   std::memcpy(H->magic, kCkptMagic, 8);
-  H->version = 3;
+  H->version = 4;
   H->header_bytes = (uint32_t)sizeof(CkptHeader);
   const lbm_ec_params& p = h->p;
   H->nx = p.nx;
@@ -1362,7 +1364,7 @@ int lbm_ec_load(lbm_ec_t* h, const void* d_src, size_t bytes) {
   EC_HIP(hipMemcpyAsync(&H, d, sizeof(H), hipMemcpyDeviceToHost, h->s));
   EC_HIP(hipStreamSynchronize(h->s));
   ckpt_fill(h, &mine, K.total);
-  if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 3 || H.header_bytes != sizeof(CkptHeader))
+  if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 4 || H.header_bytes != sizeof(CkptHeader))
     return fail(LBM_EC_EINVAL, "not a checkpoint of this library version");
   mine.steps = H.steps;
   if (std::memcmp(&H, &mine, sizeof(H)) != 0)

@@ -369,6 +369,12 @@ __device__ __forceinline__ T ldnt(const T* p) {
 // Pre-collision charge populations at (x, j), pulled from the post-collision
 // deviations G with the electrode conditions (Table I read as: injector
 // anti-bounce-back fixing rho_c = rho0, collector zero normal gradient).
+// G holds the x movers already shifted by their c_ix: plane i at column x
+// holds g*_i(x - c_ix) for i = 1, 5, 8 (c_ix = +1) and 3, 6, 7 (c_ix = -1),
+// planes 0, 2, 4 hold g*_i(x) (the collide tile stores them so, from the
+// values it keeps in LDS for the charge sums).  The streamed populations are
+// then read at the node's own column, aligned; only the injector row's
+// reflections of the same node's g*_7, g*_8 read one column aside.
 template <typename T>
 __device__ __forceinline__ void pull_g(const Consts& c, const T* __restrict__ G, const T* __restrict__ rows,
                                        int x, int j, T g[9]) {
@@ -381,13 +387,13 @@ __device__ __forceinline__ void pull_g(const Consts& c, const T* __restrict__ G,
   const T* p2 = G + (lo ? 2 : 4) * plane;
   const T* p5 = G + (lo ? 5 : 7) * plane;
   const T* p6 = G + (lo ? 6 : 8) * plane;
-  const unsigned o2 = rb + x, o5 = rb + (lo ? xm : x), o6 = rb + (lo ? xp : x);
+  const unsigned o2 = rb + x, o5 = rb + (lo ? x : xm), o6 = rb + (lo ? x : xp);
   // above the node: streamed from row j+1, or the same-row neighbours at the
   // collector (zero normal gradient)
-  const unsigned o4 = ra + x, o7 = ra + xp, o8 = ra + xm;
+  const unsigned o4 = ra + x, o7 = ra + x, o8 = ra + x;
   const T a0 = ldnt(&G[row + x]);
-  const T a1 = ldnt(&G[plane + row + xm]);
-  const T a3 = ldnt(&G[3 * plane + row + xp]);
+  const T a1 = ldnt(&G[plane + row + x]);
+  const T a3 = ldnt(&G[3 * plane + row + x]);
   const T a2 = ldnt(&p2[o2]), a5 = ldnt(&p5[o5]), a6 = ldnt(&p6[o6]);
   const T a4 = ldnt(&G[4 * plane + o4]), a7 = ldnt(&G[7 * plane + o7]), a8 = ldnt(&G[8 * plane + o8]);
   const T ua = rows[ROW_DG_UP_AXIS * c.ny + j], ud = rows[ROW_DG_UP_DIAG * c.ny + j];
@@ -436,6 +442,18 @@ __device__ __forceinline__ void local_pop(const Consts& c, const T* __restrict__
   const size_t idx = (size_t)j * c.P + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) a[i] = A[i * plane + idx];
+}
+
+// The post-collision charge populations g*_i(x, j) of node (x, j) from G as
+// the collide stores it (x movers at column x + c_ix; see pull_g).
+template <typename T>
+__device__ __forceinline__ void local_post_g(const Consts& c, const T* __restrict__ G, int x, int j, T a[9]) {
+  const size_t plane = (size_t)c.ny * c.P;
+  const size_t row = (size_t)j * c.P;
+  const int xm = wrap_m(x, c.nx), xp = wrap_p(x, c.nx);
+  const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) a[i] = G[i * plane + row + (cx[i] > 0 ? xp : (cx[i] < 0 ? xm : x))];
 }
 
 // Where the forward transform takes the charge density deviation rho_c - r
@@ -1275,7 +1293,9 @@ __device__ __forceinline__ int xcd_order(int b, int G) {
 // mom == nullptr: no moments are emitted.  STORE false: nothing is written
 // (a halo column of an x-tile, whose node belongs to the neighbouring tile).
 // gout receives the post-collision charge populations as stored (rounded
-// to T), for the charge density of the next step.
+// to T), for the charge density of the next step; of them the node stores
+// g*_0, g*_2, g*_4 itself, and the tile stores the x movers, shifted (see
+// pull_g and collide_tile).
 template <typename T, typename C, bool PULL, bool STORE = true>
 __device__ __forceinline__ void collide_node(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
                                              T* __restrict__ Fout, T* __restrict__ Gout,
@@ -1359,7 +1379,7 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
     gout[i] = (T)gv;
     if constexpr (STORE) {
       __builtin_nontemporal_store((T)fv, &Fout[i * plane + idx]);
-      __builtin_nontemporal_store(gout[i], &Gout[i * plane + idx]);
+      if (i == 0 || i == 2 || i == 4) __builtin_nontemporal_store(gout[i], &Gout[i * plane + idx]);
     }
   };
   {  // rest direction
@@ -1417,13 +1437,19 @@ __device__ __forceinline__ void collide_node(const Consts& c, const T* __restric
 // tune.  Written: rq (the density of rows j0 .. j1-1, without U from row
 // j0-1 and without D from row j1), eu[b] = U of row j1-1 and ed[b] = D of row
 // j0 (the forward transform adds them across the tile edges).  All sums in
-// T, in a fixed order.
+// T, in a fixed order.  The x movers of G are stored from LDS already shifted
+// (column x receives g*_1, g*_5, g*_8 of x - 1 and g*_3, g*_6, g*_7 of x + 1),
+// the values the sums read there anyway: the next pull then reads every
+// plane at the node's column, and loads that straddle cache lines (which the
+// streaming loads do not keep for the neighbouring wave) are avoided for
+// those six planes.
 //
 // LDS: the six x movers of the current row (in a narrower tile with a halo
 // slot at each end), own g*_4, the incomplete P of the current and of the
 // previous row, U.
 // DENS: no collision; g* is read from Gin as stored (the density of a state
-// whose post-collision populations were changed in place).
+// whose post-collision populations were changed in place); nothing else is
+// written.
 template <typename T, typename C, bool PULL, bool EMIT, bool DENS = false>
 __device__ __forceinline__ void collide_tile(const Consts& c, const T* __restrict__ Fin, const T* __restrict__ Gin,
                                              T* __restrict__ Fout, T* __restrict__ Gout, const T* __restrict__ phi,
@@ -1466,7 +1492,7 @@ __device__ __forceinline__ void collide_tile(const Consts& c, const T* __restric
       x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
       T gt[9];
       if constexpr (DENS) {
-        local_pop<T>(c, Gin, x, r, gt);
+        local_post_g<T>(c, Gin, x, r, gt);
       } else {
         if (q < tw)
           collide_node<T, C, PULL>(c, Fin, Gin, Fout, Gout, phi, rows, rowsd, EMIT ? mom : nullptr, x, r, gt);
@@ -1497,6 +1523,15 @@ __device__ __forceinline__ void collide_tile(const Consts& c, const T* __restric
         rq[(size_t)(r - 1) * c.P + x] = Pprev[xl] + D;
       else if (r > 0)
         ed[(size_t)b * c.P + x] = D;
+      if constexpr (!DENS) {
+        const size_t pl = (size_t)ny * c.P, k = (size_t)r * c.P + x;
+        __builtin_nontemporal_store(m1[sm], &Gout[pl + k]);
+        __builtin_nontemporal_store(m5[sm], &Gout[5 * pl + k]);
+        __builtin_nontemporal_store(m8[sm], &Gout[8 * pl + k]);
+        __builtin_nontemporal_store(m3[sp], &Gout[3 * pl + k]);
+        __builtin_nontemporal_store(m6[sp], &Gout[6 * pl + k]);
+        __builtin_nontemporal_store(m7[sp], &Gout[7 * pl + k]);
+      }
       const T P = (Pcur[xl] + m1[sm]) + m3[sp];
       const T U = (Ua[xl] + m5[sm]) + m6[sp];
       Pcur[xl] = P;
@@ -1806,7 +1841,8 @@ __global__ void __launch_bounds__(256) k_stats_part(Consts c, const double* __re
 // anti-bounce-back replaces each outgoing g*_i by 2 w_i rho0 - g*_i) and net
 // in through the collector (the incoming populations copy the last row, the
 // outgoing ones leave).  On deviations the reference rows cancel except in
-// the injector constants g_abb = 2 w_i (rho0 - r(0)).
+// the injector constants g_abb = 2 w_i (rho0 - r(0)).  Whole-row sums, so
+// the x shift of the stored movers (see pull_g) leaves them unchanged.
 template <typename T>
 __global__ void __launch_bounds__(256) k_stats_final(Consts c, const double* __restrict__ part, int nb,
                                                      const T* __restrict__ G, double* __restrict__ out) {
@@ -1988,7 +2024,8 @@ __global__ void __launch_bounds__(256) kb_stats_advance(SlotDesc* __restrict__ D
       }
       // collector current: what leaves through the upper electrode in the
       // next streaming, from the post-collision populations just written
-      // (the reference rows cancel between the up and the down directions)
+      // (the reference rows cancel between the up and the down directions;
+      // a whole-row sum, so the x shift of the stored movers does not matter)
       const T* G = (const T*)d.b.g[1 - d.cur];
       const size_t plane = (size_t)ny * d.c.P, top = (size_t)(ny - 1) * d.c.P;
       double cur_out = 0;

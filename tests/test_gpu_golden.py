@@ -110,20 +110,20 @@ def _cfg2(step):
     return gold
 
 
-@pytest.mark.parametrize("precision", ["fp32_f64math", "fp32"])
-def test_cfg2_prefix_against_oracle(precision):
-    """4096 x 4096 after 100 steps (FP32 storage; FP64 storage is limited to
-    nx <= 2048): every field within 1e-5."""
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32_f64math", 1e-5), ("fp32", 1e-5)])
+def test_cfg2_prefix_against_oracle(precision, tol):
+    """4096 x 4096 after 100 steps (FP64 storage runs x-tiled collide tiles
+    at this row length): every field within the precision's tolerance."""
     gold = _cfg2(100)
     res = _run(precision, [100], KW2)
-    _gate(gold, res, [100], precision, 1e-5, gate_u=True)
+    _gate(gold, res, [100], precision, tol, gate_u=True)
 
 
-@pytest.mark.parametrize("precision", ["fp32_f64math"])
-def test_cfg2_full_against_oracle(precision):
+@pytest.mark.parametrize("precision,tol", [("fp32_f64math", 1e-5), ("fp64", 1e-11)])
+def test_cfg2_full_against_oracle(precision, tol):
     """4096 x 4096 after the workload's 1000 steps, in the precision mode the
-    benchmark times (launch shapes never change results): every field within
-    1e-5."""
+    benchmark times (launch shapes never change results) and in FP64: every
+    field within the precision's tolerance."""
     gold = _cfg2(1000)
     res = _run(precision, [1000], KW2)
-    _gate(gold, res, [1000], precision, 1e-5, gate_u=True)
+    _gate(gold, res, [1000], precision, tol, gate_u=True)
