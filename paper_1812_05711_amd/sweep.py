@@ -148,11 +148,14 @@ def main(argv=None):
                     help="NXxNY: instead of the seeded sweep, the Eq. 29 threshold problem at this grid for the "
                          "T values of --T; prints the growth rates and their zero crossing")
     ap.add_argument("--T", default="160,162,164,166", help="T values of --threshold (comma separated)")
+    ap.add_argument("--Lambda", type=float, default=0.25,
+                    help="fluid TRT parameter of Eq. 17 for --threshold (the paper's study uses 1/12)")
+    ap.add_argument("--tau-plus", type=float, default=0.8, help="fluid tau+ for --threshold")
     args = ap.parse_args(argv)
     if args.threshold:
         nx, ny = (int(v) for v in args.threshold.lower().split("x"))
         Ts = [float(v) for v in args.T.split(",")]
-        cfgs = threshold_configs(nx, ny, Ts, precision=args.precision)
+        cfgs = threshold_configs(nx, ny, Ts, precision=args.precision, Lambda=args.Lambda, tau_plus=args.tau_plus)
         import sys
 
         r = run_batched(cfgs, args.steps, emit_every=args.emit_every, tune=args.tuning is None,
