@@ -103,6 +103,19 @@ def test_cfg1_fp32_arithmetic_velocity_regression_bound():
     assert e["u"] <= 3e-4, e
 
 
+@pytest.mark.xfail(strict=True, reason="FP32 collision arithmetic misses the 1e-5 gate on u after 10000 "
+                   "steps; the precision notes of the design document give the measured level and the "
+                   "experiments on its cause (strict: a pass would mean the gate is met and this mark goes)")
+def test_cfg1_fp32_arithmetic_velocity_gate():
+    """The parity gate on u for FP32 storage with FP32 collision arithmetic,
+    expected to fail until that mode meets it."""
+    gold = _golden(GOLDEN, "1024 x 840", "cfg1")
+    if 10000 not in _snapshots(gold):
+        pytest.skip("1024 x 840 oracle golden has no step 10000 yet")
+    res = _run("fp32", [10000], KW)
+    _gate(gold, res, [10000], "fp32", 1e-5, gate_u=True)
+
+
 def _cfg2(step):
     gold = _golden(GOLDEN2, "4096 x 4096", "cfg2")
     if step not in _snapshots(gold):
