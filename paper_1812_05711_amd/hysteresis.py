@@ -168,7 +168,7 @@ def main(argv=None):
     ap.add_argument("--start-t0", type=float, default=12.0, help="ionic times at the first falling stage")
     ap.add_argument("--dwell-t0", type=float, default=4.0, help="ionic times at each later stage")
     ap.add_argument("--precision", default="fp32_f64math", choices=["fp64", "fp32", "fp32_f64math"])
-    ap.add_argument("--tuning", default=None, help="fft_threads,collide_bx,collide_by (default: autotuned)")
+    ap.add_argument("--tuning", default=None, help="fft_threads,collide_bx,collide_by[,collide_tw] (default: autotuned)")
     ap.add_argument("--Lambda", type=float, default=0.25, help="fluid TRT parameter of Eq. 17 (the paper's is 1/12)")
     ap.add_argument("--tau-plus", type=float, default=0.8, help="fluid tau+")
     args = ap.parse_args(argv)

@@ -143,7 +143,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--emit-every", type=int, default=100)
     ap.add_argument("--precision", default="fp32_f64math", choices=["fp64", "fp32", "fp32_f64math"])
-    ap.add_argument("--tuning", default=None, help="fft_threads,collide_bx,collide_by (default: autotuned)")
+    ap.add_argument("--tuning", default=None, help="fft_threads,collide_bx,collide_by[,collide_tw] (default: autotuned)")
     ap.add_argument("--threshold", default=None,
                     help="NXxNY: instead of the seeded sweep, the Eq. 29 threshold problem at this grid for the "
                          "T values of --T; prints the growth rates and their zero crossing")
