@@ -15,6 +15,7 @@ import os
 FFT_THREADS = (64, 128, 256, 512)
 COLLIDE_SHAPES = ((64, 1), (128, 1), (256, 1), (512, 1), (1024, 1))
 TILE_WIDTHS = (0, 1024, 512)  # 0: the library's default width
+BATCH_TILE_WIDTHS = (0, 128, 64)  # batches: whole rows, or narrower tiles for more blocks per slot
 DEFAULT = (256, 256, 1)
 
 
@@ -63,7 +64,9 @@ def _time_batch(b, steps):
 
 
 def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
-    """Best (fft_threads, collide_bx, collide_by) for this batch composition."""
+    """Best (fft_threads, collide_bx, collide_by, collide_tw) for this batch
+    composition: the transform threads, then the collide block shape, then
+    the collide tile width (each at the best of the earlier ones)."""
     from .sweep import make_batch
 
     sig = signature(configs)
@@ -71,7 +74,7 @@ def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
     if sig in cache:
         return tuple(cache[sig]["tuning"])
     # enough steps for every candidate; the throwaway batch is never polled
-    n_cand = len(FFT_THREADS) + len(COLLIDE_SHAPES)
+    n_cand = len(FFT_THREADS) + len(COLLIDE_SHAPES) + len(BATCH_TILE_WIDTHS)
     b, _ = make_batch(configs, steps=(steps + 8) * n_cand + 8, emit_every=0, device=device)
     best_fft, best_t = DEFAULT[0], float("inf")
     for ft in FFT_THREADS:
@@ -88,8 +91,14 @@ def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
         t = _time_batch(b, steps)
         if t < best_t:
             best_shape, best_t = (bx, by), t
+    best_tw = 0
+    for tw in BATCH_TILE_WIDTHS[1:]:
+        b.set_tuning(best_fft, best_shape[0], best_shape[1], tw)
+        t = _time_batch(b, steps)
+        if t < best_t:
+            best_tw, best_t = tw, t
     b.close()
-    tuning = (best_fft, best_shape[0], best_shape[1])
+    tuning = (best_fft, best_shape[0], best_shape[1], best_tw)
     cache[sig] = {"tuning": list(tuning), "ms_per_step": best_t}
     if use_cache:
         _store(cache)
