@@ -179,8 +179,10 @@ def main(argv=None):
     print(f"{len(cfgs)} instances, {nodes} nodes, {args.steps} steps, tuning {tuning}: "
           f"{dt / args.steps * 1e6:.1f} us per step, {nodes * args.steps / dt / 1e6:.0f} MLUPS", flush=True)
     for s, c in zip(slots, cfgs):
-        print(f"  ny {c['ny']:4d} nx {c['nx']:4d} T {c['T']:7.2f} growth rate "
-              f"{growth_rate(b.history(s), ionic_time(c)):+.4f}")
+        fit = growth_fit(b.history(s), ionic_time(c))
+        kind = "transient slope" if fit["transient"] else "growth rate"
+        print(f"  ny {c['ny']:4d} nx {c['nx']:4d} T {c['T']:7.2f} {kind} {fit['rate']:+.4f} per ionic time "
+              f"(the run covers {fit['span']:.3f} ionic times; r2 of the fit {fit['r2']:.4f})")
     b.close()
 
 
