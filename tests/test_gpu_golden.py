@@ -91,16 +91,18 @@ def test_cfg1_against_oracle(precision, tol):
 
 def test_cfg1_fp32_arithmetic_velocity_regression_bound():
     """Not a parity test: FP32 storage with FP32 collision arithmetic misses
-    the 1e-5 gate on u (1.4e-4 of max |u| after 10000 steps; the design notes
+    the 1e-5 gate on u (8.3e-5 of max |u| after 10000 steps; the design notes
     give the experiments that place the error in the fluid collision's FP32
     arithmetic as a whole).  FP32 storage meets the gate with FP64 collision
-    arithmetic (test_cfg1_against_oracle[fp32_f64math]).  This bound, twice the
-    measured level, only catches a regression of the FP32-arithmetic mode."""
+    arithmetic (test_cfg1_against_oracle[fp32_f64math]).  This bound, about
+    twice the measured level, only catches a regression of the FP32-arithmetic
+    mode (test_cfg1_fp32_arithmetic_velocity_gate is the gate itself, marked as
+    an expected failure)."""
     gold = _golden(GOLDEN, "1024 x 840", "cfg1")
     snaps = _snapshots(gold)
     res = _run("fp32", snaps, KW)
     e = _gate(gold, res, snaps, "fp32", 1e-5, gate_u=False)
-    assert e["u"] <= 3e-4, e
+    assert e["u"] <= 2e-4, e
 
 
 @pytest.mark.xfail(strict=True, reason="FP32 collision arithmetic misses the 1e-5 gate on u after 10000 "
