@@ -10,19 +10,30 @@ full comparison would.
 
     python tests/golden/make_oracle_golden.py cfg1      # 1024 x 840, 10000 steps
     python tests/golden/make_oracle_golden.py cfg2      # 4096 x 4096, 1000 steps
+    python tests/golden/make_oracle_golden.py cfg2 --threads 7
+
+With --threads the collision of each step (86 % of an oracle step at these
+sizes: pointwise, node by node) is handed to the oracle's own Oracle.collide
+in bands of rows on a thread pool; everything else (the moments and the
+Poisson solve, the streaming) is the oracle's call on the whole grid.  The
+collision of a node reads nothing but that node, so the bands give the same
+floating-point operations on the same operands as one call on the grid:
+tests/test_golden_slab_driver.py checks the two bit for bit.
 """
 
+import argparse
 import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import Oracle, Params  # noqa: E402
+from oracle import Oracle, Params, lbm  # noqa: E402
 
 CASES = {
     # single-instance FP64 vs FP32-deviation configuration: T = 300, C = 10,
@@ -38,6 +49,43 @@ CASES = {
 }
 
 FIELDS = ("rho", "rho_m1", "ux", "uy", "rho_c", "phi")
+BAND_ROWS = 4
+
+
+class _Band:
+    """The state Oracle.collide reads (lattice constants, f, g), restricted
+    to rows [a, b) as views of the oracle's own arrays."""
+
+    def __init__(self, o, a, b):
+        self.lc = o.lc
+        self.ft = o.ft[:, a:b]
+        self.gt = o.gt[:, a:b]
+
+
+def step_in_bands(o, pool, n=1, band_rows=BAND_ROWS):
+    """n steps of o, each Oracle.step's sequence (moments, collision,
+    streaming) with the collision called band by band on the pool."""
+    if o.pending_T is not None:
+        raise ValueError("a pending change of T is left to Oracle.step")
+    ny = o.p.ny
+    bands = [(a, min(a + band_rows, ny)) for a in range(0, ny, band_rows)]
+    for _ in range(n):
+        m = o.macroscopic()
+        ft_post = np.empty_like(o.ft)
+        gt_post = np.empty_like(o.gt)
+
+        def collide_band(ab):
+            a, b = ab
+            mb = {k: (v[a:b] if np.ndim(v) == 2 else v) for k, v in m.items()}
+            ft_post[:, a:b], gt_post[:, a:b] = Oracle.collide(_Band(o, a, b), mb)
+
+        list(pool.map(collide_band, bands))
+        del m
+        fs = pool.submit(lbm.stream_fluid, ft_post, o.s_ref)
+        gs = pool.submit(lbm.stream_charge, gt_post, o.R, o.lc.rho0)
+        o.ft, o.gt = fs.result(), gs.result()
+        o.n += 1
+    return o
 
 
 def sample_rows(ny, stride):
@@ -52,10 +100,11 @@ def sample_cols(nx, stride):
     return np.array(cols)
 
 
-def main(name):
+def main(name, threads=0):
     case = CASES[name]
     p = Params(**case["params"])
     o = Oracle(p)
+    pool = ThreadPoolExecutor(threads) if threads > 1 else None
     rows = sample_rows(p.ny, case["stride"])
     cols = sample_cols(p.nx, case["stride"])
     out = {"rows": rows, "cols": cols}
@@ -65,7 +114,11 @@ def main(name):
     t = time.time()
     for snap in case["snapshots"]:
         while o.n < snap:
-            o.step(min(50, snap - o.n))
+            k = min(50, snap - o.n)
+            if pool is None:
+                o.step(k)
+            else:
+                step_in_bands(o, pool, k)
             print(f"{name}: step {o.n} after {time.time() - t:.0f} s", flush=True)
         f = o.fields()
         for k in FIELDS:
@@ -83,4 +136,9 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    ap = argparse.ArgumentParser()
+    ap.add_argument("case", choices=sorted(CASES))
+    ap.add_argument("--threads", type=int, default=0,
+                    help="collide in bands of rows on this many threads (0: Oracle.step)")
+    a = ap.parse_args()
+    main(a.case, a.threads)
