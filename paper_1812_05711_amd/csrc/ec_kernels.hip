@@ -142,28 +142,47 @@ __device__ __forceinline__ void stockham_pass(const C2<T>* __restrict__ src, C2<
   }
 }
 
-// Pass of any other radix R: one thread per output (q, t), a direct DFT of
-// the R inputs with the combined twiddle exp(s 2 pi i r (k N/(Ns R) + q N/R) / N).
+// Pass of any other radix R: a direct DFT of the R inputs per output (q, t)
+// with the combined twiddle exp(s 2 pi i r (k N/(Ns R) + q N/R) / N).  Each
+// output's sum is split at h = (R + 1) / 2: terms 0 .. h-1 by a thread of the
+// block's first half, terms h .. R-1 by its partner in the second half, each
+// in order, then added (the same order whatever the block size; the chain of
+// dependent terms per thread is halved, and a transform shorter than the
+// block keeps both halves busy).
 template <typename T, bool INV>
 __device__ __forceinline__ void generic_pass(const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
                                              int N, int Ns, int R, const C2<T>* __restrict__ tw) {
   const int stride = N / R;
   const int twstep = N / (Ns * R);
-  for (int o = threadIdx.x; o < N; o += blockDim.x) {
-    const int q = o / stride;
-    const int t = o - q * stride;
-    const int k = t % Ns;
-    const int e = (k * twstep + q * stride) % N;
-    C2<T> acc = src[t];
-    int idx = e;
-    for (int r = 1; r < R; ++r) {
-      C2<T> w = tw[idx];
-      if (INV) w.im = -w.im;
-      acc = cadd(acc, cmul(src[t + r * stride], w));
-      idx += e;
-      if (idx >= N) idx -= N;
+  const int h = (R + 1) / 2;
+  const int half = blockDim.x / 2;
+  const bool side = threadIdx.x >= half;
+  const int lo = threadIdx.x - (side ? half : 0);
+  for (int ob = 0; ob < N; ob += half) {
+    const int o = ob + lo;
+    C2<T> acc = {T(0), T(0)};
+    int pos = 0;
+    if (o < N) {
+      const int q = o / stride;
+      const int t = o - q * stride;
+      const int k = t % Ns;
+      const int e = (k * twstep + q * stride) % N;
+      const int r0 = side ? h : 1, r1 = side ? R : h;
+      int idx = (e * r0) % N;
+      if (!side) acc = src[t];
+#pragma unroll 4
+      for (int r = r0; r < r1; ++r) {
+        C2<T> w = tw[idx];
+        if (INV) w.im = -w.im;
+        acc = cadd(acc, cmul(src[t + r * stride], w));
+        idx += e;
+        if (idx >= N) idx -= N;
+      }
+      pos = (t / Ns) * Ns * R + k + q * Ns;
+      if (side) dst[pos] = acc;
     }
-    dst[(t / Ns) * Ns * R + k + q * Ns] = acc;
+    __syncthreads();
+    if (o < N && !side) dst[pos] = cadd(acc, dst[pos]);
   }
 }
 

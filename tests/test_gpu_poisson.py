@@ -24,8 +24,12 @@ pytestmark = pytest.mark.gpu
 
 BASE = dict(T=200.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25, Lambda_g=1e-6, noise_amp=1e-3,
             seed=181205711)
+# (61, 50), (122, 30), (77, 40): direct DFT passes of prime radix (61; 7 and 11)
+# with the twiddle table copied to LDS; (4094, 24) = 2 x 23 x 89: the copy
+# fits beside the FP32 ping-pong buffers, not beside the FP64 ones (there the
+# direct passes read the table from global memory)
 CASES = [(16, 20), (24, 40), (40, 840), (8, 4096), (6, 8224), (6, 8256), (6, 16480), (2048, 24), (4096, 24),
-         (8192, 8), (1000, 24), (122, 30)]
+         (8192, 8), (1000, 24), (122, 30), (61, 50), (77, 40), (4094, 24)]
 TOL = {"fp64": 1e-11, "fp32_f64math": 1e-6, "fp32": 1e-6}
 
 
