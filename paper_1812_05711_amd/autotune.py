@@ -50,20 +50,26 @@ def _store(cache):
         pass
 
 
-def _time_batch(b, steps):
+BATCH_REPS = 2  # timings per candidate (the best one counts): single short timings picked noise
+
+
+def _time_batch(b, steps, reps=BATCH_REPS):
     import torch
 
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     b.step(8)  # capture and warm up
-    start.record(b.stream)
-    b.step(steps)
-    end.record(b.stream)
-    end.synchronize()
-    return start.elapsed_time(end) / steps
+    best = float("inf")
+    for _ in range(reps):
+        start.record(b.stream)
+        b.step(steps)
+        end.record(b.stream)
+        end.synchronize()
+        best = min(best, start.elapsed_time(end) / steps)
+    return best
 
 
-def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
+def tune_batch(configs, device="cuda:0", steps=64, use_cache=True):
     """Best (fft_threads, collide_bx, collide_by, collide_tw) for this batch
     composition: the transform threads, then the collide block shape, then
     the collide tile width (each at the best of the earlier ones)."""
@@ -75,7 +81,7 @@ def tune_batch(configs, device="cuda:0", steps=32, use_cache=True):
         return tuple(cache[sig]["tuning"])
     # enough steps for every candidate; the throwaway batch is never polled
     n_cand = len(FFT_THREADS) + len(COLLIDE_SHAPES) + len(BATCH_TILE_WIDTHS)
-    b, _ = make_batch(configs, steps=(steps + 8) * n_cand + 8, emit_every=0, device=device)
+    b, _ = make_batch(configs, steps=(BATCH_REPS * steps + 8) * n_cand + 8, emit_every=0, device=device)
     best_fft, best_t = DEFAULT[0], float("inf")
     for ft in FFT_THREADS:
         b.set_tuning(ft, DEFAULT[1], DEFAULT[2])

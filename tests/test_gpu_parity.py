@@ -42,11 +42,13 @@ def _check(kw, steps, tol, fields=("rho", "rho_m1", "u", "rho_c", "phi")):
     (8, 3, 10),
     (1, 16, 40),
     (200, 33, 20),
-    # collide tiles of 2, 4 and 16 rows, full and partial last tiles
+    # collide tiles of 2, 4, 15 and 8 rows, full and partial last tiles
     (8, 520, 30),
     (6, 1100, 20),
     (5, 1027, 20),
+    (4, 4000, 10),
     (3, 4200, 10),
+    (3, 4100, 10),
 ])
 def test_fp64_small(nx, ny, steps):
     _check(dict(BASE, nx=nx, ny=ny), steps, TOL64)
