@@ -54,12 +54,14 @@ def _errors(gold, f, step):
     return e
 
 
-def _run(precision, snaps, kw):
+def _run(precision, snaps, kw, tuning=None):
     import torch
 
     from paper_1812_05711_amd.lbm_ec import Simulation
 
     sim = Simulation(device="cuda:0", precision=precision, **kw)
+    if tuning is not None:
+        sim.set_tuning(*tuning)
     out = {}
     for s in snaps:
         sim.step(s - sim.steps_done())
@@ -134,11 +136,28 @@ def test_cfg2_prefix_against_oracle(precision, tol):
     _gate(gold, res, [100], precision, tol, gate_u=True)
 
 
+def _bench_tuning(precision, kw):
+    """The launch shapes bench.py times: its autotuner run on a throwaway
+    instance of the same workload."""
+    import torch
+
+    from paper_1812_05711_amd import autotune
+    from paper_1812_05711_amd.lbm_ec import Simulation
+
+    sim = Simulation(device="cuda:0", precision=precision, **kw)
+    tuning, _ = autotune.tune_single(sim, steps=8)
+    torch.cuda.synchronize()
+    sim.close()
+    return tuning
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32_f64math", 1e-5), ("fp64", 1e-11)])
 def test_cfg2_full_against_oracle(precision, tol):
     """4096 x 4096 after the workload's 1000 steps, in the precision mode the
-    benchmark times (launch shapes never change results) and in FP64: every
-    field within the precision's tolerance."""
+    benchmark times and in FP64, each in the launch shapes the benchmark's
+    autotuner picks: every field within the precision's tolerance."""
     gold = _cfg2(1000)
-    res = _run(precision, [1000], KW2)
+    tuning = _bench_tuning(precision, KW2)
+    print(precision, "launch shapes", tuning, flush=True)
+    res = _run(precision, [1000], KW2, tuning)
     _gate(gold, res, [1000], precision, tol, gate_u=True)
