@@ -10,7 +10,8 @@ full comparison would.
 
     python tests/golden/make_oracle_golden.py cfg1      # 1024 x 840, 10000 steps
     python tests/golden/make_oracle_golden.py cfg2      # 4096 x 4096, 1000 steps
-    python tests/golden/make_oracle_golden.py cfg2 --threads 7
+    MALLOC_MMAP_MAX_=0 MALLOC_TRIM_THRESHOLD_=68719476736 \
+        python tests/golden/make_oracle_golden.py cfg2 --threads 7
 
 With --threads the collision of each step (86 % of an oracle step at these
 sizes: pointwise, node by node) is handed to the oracle's own Oracle.collide
@@ -18,7 +19,10 @@ in bands of rows on a thread pool; everything else (the moments and the
 Poisson solve, the streaming) is the oracle's call on the whole grid.  The
 collision of a node reads nothing but that node, so the bands give the same
 floating-point operations on the same operands as one call on the grid:
-tests/test_golden_slab_driver.py checks the two bit for bit.
+tests/test_golden_slab_driver.py checks the two bit for bit.  The glibc
+settings keep freed arrays in the heap for the next step (fresh GB-sized
+arrays otherwise cost about half of each step in page faults at this size);
+they change no arithmetic.
 """
 
 import argparse
