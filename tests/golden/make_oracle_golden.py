@@ -15,10 +15,12 @@ full comparison would.
 
 With --threads the collision of each step (86 % of an oracle step at these
 sizes: pointwise, node by node) is handed to the oracle's own Oracle.collide
-in bands of rows on a thread pool; everything else (the moments and the
-Poisson solve, the streaming) is the oracle's call on the whole grid.  The
-collision of a node reads nothing but that node, so the bands give the same
-floating-point operations on the same operands as one call on the grid:
+in bands of rows on a thread pool, and the oracle's node-wise moments, row
+transforms and per-wavenumber Thomas solve run on bands of rows (or
+wavenumber columns) as well; the rest (mean mode, field, streaming) is the
+oracle's call on the whole grid.  Each of these computes an element from its
+own node, row or column alone, so the bands give the same floating-point
+operations on the same operands as one call on the grid:
 tests/test_golden_slab_driver.py checks the two bit for bit.  The glibc
 settings keep freed arrays in the heap for the next step (fresh GB-sized
 arrays otherwise cost about half of each step in page faults at this size);
@@ -37,7 +39,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import Oracle, Params, lbm  # noqa: E402
+from oracle import Oracle, Params, lbm, poisson  # noqa: E402
 
 CASES = {
     # single-instance FP64 vs FP32-deviation configuration: T = 300, C = 10,
@@ -66,15 +68,81 @@ class _Band:
         self.gt = o.gt[:, a:b]
 
 
+def _row_banded(fn, pool, bands, lead):
+    """fn applied band by band along the row axis (axis `lead` of its array
+    arguments; `lead` = 1 for population stacks (9, ny, nx), 0 for fields
+    (ny, nx)), the results written into one output per return value."""
+
+    def wrapped(*args):
+        def part(ab):
+            a, b = ab
+            return fn(*[x[:, a:b] if (lead == 1 and x.ndim == 3) else x[a:b] for x in args])
+
+        parts = list(pool.map(part, bands))
+        first = parts[0]
+        if isinstance(first, tuple):
+            return tuple(np.concatenate([p[i] for p in parts], axis=0) for i in range(len(first)))
+        return np.concatenate(parts, axis=0)
+
+    return wrapped
+
+
+def _column_banded(fn, pool, ncols, width=256):
+    """fn of (n, nx) arrays, independent per trailing index, applied to
+    bands of columns."""
+    bands = [(a, min(a + width, ncols)) for a in range(0, ncols, width)]
+
+    def wrapped(*args):
+        parts = list(pool.map(lambda ab: fn(*[x[:, ab[0]:ab[1]] for x in args]), bands))
+        return np.concatenate(parts, axis=1)
+
+    return wrapped
+
+
+class _BandedMoments:
+    """Within the block, the oracle's node-wise moments (Eq. 5-7), its row
+    transforms (Eq. 19) and its per-wavenumber Thomas solve run band by band
+    on the pool: the module functions Oracle.macroscopic reaches are swapped
+    for wrappers that call the originals on bands of rows (or, for the
+    Thomas solve, of wavenumber columns) and stack the results; every
+    element is computed by the same function from the same operands."""
+
+    def __init__(self, o, pool, bands):
+        nx = o.p.nx
+        self.swaps = [
+            (lbm, "charge_deviation", _row_banded(lbm.charge_deviation, pool, bands, 1)),
+            (lbm, "density_deviation", _row_banded(lbm.density_deviation, pool, bands, 1)),
+            (lbm, "velocity", _row_banded(lbm.velocity, pool, bands, 1)),
+            (poisson, "dft_x", _row_banded(poisson.dft_x, pool, bands, 0)),
+            (poisson, "idft_x", _row_banded(poisson.idft_x, pool, bands, 0)),
+            (poisson, "thomas", _column_banded(poisson.thomas, pool, nx)),
+        ]
+        self.saved = []
+
+    def __enter__(self):
+        for mod, name, fn in self.swaps:
+            self.saved.append((mod, name, getattr(mod, name)))
+            setattr(mod, name, fn)
+        return self
+
+    def __exit__(self, *exc):
+        for mod, name, fn in self.saved:
+            setattr(mod, name, fn)
+        return False
+
+
 def step_in_bands(o, pool, n=1, band_rows=BAND_ROWS):
     """n steps of o, each Oracle.step's sequence (moments, collision,
-    streaming) with the collision called band by band on the pool."""
+    streaming) with the collision called band by band on the pool, and the
+    moments' node-wise parts and row transforms in bands as well."""
     if o.pending_T is not None:
         raise ValueError("a pending change of T is left to Oracle.step")
     ny = o.p.ny
     bands = [(a, min(a + band_rows, ny)) for a in range(0, ny, band_rows)]
+    mbands = [(a, min(a + 4 * band_rows, ny)) for a in range(0, ny, 4 * band_rows)]
     for _ in range(n):
-        m = o.macroscopic()
+        with _BandedMoments(o, pool, mbands):
+            m = o.macroscopic()
         ft_post = np.empty_like(o.ft)
         gt_post = np.empty_like(o.gt)
 

@@ -2,9 +2,11 @@
 Oracle.step: the same populations bit for bit.
 
 The driver hands the collision of each step to Oracle.collide in bands of
-rows on a thread pool; a node's collision reads only that node, so every
-band sees the same operands and performs the same operations as the single
-call on the whole grid.  These cases make any slip in the band bookkeeping
+rows on a thread pool, and runs the oracle's moments, row transforms and
+per-wavenumber Thomas solve on bands of rows (or wavenumber columns); each
+of these computes every element from that element's own row or column
+alone, so every band sees the same operands and performs the same
+operations as the single call on the whole grid.  These cases make any slip in the band bookkeeping
 (a row missed or written twice, a band given another band's moments, the
 wrong reference rows in the streaming) show as a bit difference.
 """
@@ -36,6 +38,9 @@ CASES = [
     # Eq. 29 start, another Lambda, a grid narrower than one band is tall
     dict(nx=9, ny=24, T=200.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=1.0, Lambda=1 / 12,
          Lambda_g=1e-6, init_mode="eq29", seed=7),
+    # rows longer than a band of wavenumber columns (600 = 256 + 256 + 88)
+    dict(nx=600, ny=21, T=400.0, C=10.0, M=10.0, Fe=4000.0, tau_plus=0.8, Lambda=0.25,
+         Lambda_g=1e-6, noise_amp=1e-3, seed=3),
 ]
 
 
